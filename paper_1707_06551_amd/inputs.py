@@ -1,0 +1,116 @@
+"""Seeded synthetic workloads (sphere placements and right-hand-side draws).
+
+This module holds no arithmetic of the boundary integral method: it only draws random
+numbers and places spheres.  Both the HIP path and the CPU oracle consume its outputs.
+
+Placement: random sequential addition.  Centres are drawn i.i.d. uniform in
+[1, L-1]^3 (so each unit sphere lies inside [0, L]^3) and a draw is rejected when its
+surface gap to any accepted sphere is below ``min_gap``.  For a target volume fraction
+phi, L = (n * 4 pi / 3 / phi)^(1/3).
+
+Right-hand sides are drawn from the same generator after placement.
+"""
+import math
+
+import numpy as np
+
+# Workloads of the benchmark suite: spheres, SH order, volume fraction or box, gap, problem.
+WORKLOADS = {
+    "spheres8_p8": dict(n=8, p=8, box=8.0, min_gap=0.5, problem="resistance", tol=1e-10),
+    "spheres512_p12": dict(n=512, p=12, phi=0.10, min_gap=0.2, problem="mobility", tol=1e-8),
+    "spheres4096_p8": dict(n=4096, p=8, phi=0.15, min_gap=0.1, problem="resistance", tol=1e-8),
+    "spheres1024_p16": dict(n=1024, p=16, phi=0.30, min_gap=0.02, problem="resistance", tol=1e-8),
+    "spheres2048_p12_slip": dict(n=2048, p=12, phi=0.25, min_gap=0.02, problem="mobility_slip", tol=1e-8),
+    "spheres64_p16_train": dict(n=64, p=16, phi=0.25, min_gap=0.02, problem="resistance", tol=1e-10),
+}
+
+
+def box_side(n, phi):
+    return (n * 4.0 * math.pi / 3.0 / phi) ** (1.0 / 3.0)
+
+
+def place_spheres(n, box, min_gap, rng, max_tries=2_000_000):
+    """Random sequential addition of n unit spheres in [0, box]^3 (centres in
+    [1, box-1]^3) with pairwise surface gap >= min_gap.  Uses a uniform cell list."""
+    lo, hi = 1.0, box - 1.0
+    dmin = 2.0 + min_gap
+    dmin2 = dmin * dmin
+    ncell = max(1, int((hi - lo) / dmin))
+    h = (hi - lo) / ncell
+    cells = {}
+    out = np.empty((n, 3))
+    k = 0
+    tries = 0
+    reach = int(math.ceil(dmin / h))
+    while k < n:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError(f"placement stalled after {k} of {n} spheres")
+        c = lo + (hi - lo) * rng.random(3)
+        ci = tuple(np.minimum(((c - lo) / h).astype(int), ncell - 1))
+        ok = True
+        for dx in range(-reach, reach + 1):
+            for dy in range(-reach, reach + 1):
+                for dz in range(-reach, reach + 1):
+                    lst = cells.get((ci[0] + dx, ci[1] + dy, ci[2] + dz))
+                    if not lst:
+                        continue
+                    d = out[lst] - c
+                    if np.any(np.einsum("ij,ij->i", d, d) < dmin2):
+                        ok = False
+                        break
+                if not ok:
+                    break
+            if not ok:
+                break
+        if ok:
+            out[k] = c
+            cells.setdefault(ci, []).append(k)
+            k += 1
+    return out
+
+
+def make_workload(name, seed=0):
+    """Centres and right-hand-side data of a named workload.
+
+    resistance:     v, omega ~ N(0, 1) per component
+    mobility:       F, T ~ N(0, 1)
+    mobility_slip:  F = T = 0 and slip coefficients ~ N(0, 1) (see ``slip_field``)
+    """
+    cfg = dict(WORKLOADS[name])
+    rng = np.random.default_rng(seed)
+    box = cfg.get("box") or box_side(cfg["n"], cfg["phi"])
+    centres = place_spheres(cfg["n"], box, cfg["min_gap"], rng)
+    n = cfg["n"]
+    cfg["box"] = box
+    out = dict(name=name, seed=seed, centres=centres, **cfg)
+    if cfg["problem"] == "resistance":
+        out["v"] = rng.standard_normal((n, 3))
+        out["omega"] = rng.standard_normal((n, 3))
+    elif cfg["problem"] == "mobility":
+        out["F"] = rng.standard_normal((n, 3))
+        out["T"] = rng.standard_normal((n, 3))
+    else:
+        out["F"] = np.zeros((n, 3))
+        out["T"] = np.zeros((n, 3))
+        out["slip_coef"] = rng.standard_normal((n, len(MONOMIALS4), 3))
+    return out
+
+
+MONOMIALS4 = [(a, b, c) for a in range(5) for b in range(5) for c in range(5) if a + b + c <= 4]
+
+
+def slip_field(slip_coef, normals, sphere_of):
+    """Tangential active slip of degree <= 4 (a squirmer-like surface velocity):
+    u_s(n) = (I - n n^T) sum_alpha C_alpha n^alpha for each node with unit normal n,
+    C drawn per sphere.  normals (N, 3), sphere_of (N,) -> (N, 3)."""
+    n = np.asarray(normals, dtype=np.float64)
+    C = slip_coef[sphere_of]                                  # (N, 35, 3)
+    mono = np.stack([n[:, 0] ** a * n[:, 1] ** b * n[:, 2] ** c for (a, b, c) in MONOMIALS4], axis=1)
+    u = np.einsum("nk,nkc->nc", mono, C)
+    return u - np.sum(u * n, axis=1)[:, None] * n
+
+
+def random_density(n_nodes, rng):
+    """A random node density (N, 3) ~ N(0, 1) for matvec parity tests."""
+    return rng.standard_normal((n_nodes, 3))
