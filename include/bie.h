@@ -1,0 +1,164 @@
+/*
+ * bie.h - C ABI of the MI355X boundary-integral library for suspensions of unit spheres
+ * in Stokes flow (Corona & Veerapaneni, "Boundary integral equation analysis for
+ * suspension of spheres in Stokes flow", arXiv:1707.06551).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Viscosity 1 (Section 5).  All spheres have radius 1.
+ * - Grid (Eq. 4.2): p+1 Gauss-Legendre latitudes (theta ascending) x n_phi uniform
+ *   longitudes phi_l = 2 pi l / n_phi.  P = (p+1) n_phi nodes per sphere, N = n_b P.
+ *   Node order: g = k*P + j*n_phi + l (sphere k, latitude j, longitude l).
+ *   Band limit of the vector transform: n <= p, |m| <= mmax = min(p, n_phi/2 - 1).
+ * - Node fields (densities, velocities) are N x 3 row-major float64 arrays.
+ * - Pointers documented "device" are HIP device pointers; the library orders all its
+ *   device work on the stream given in bie_opts (NULL = the legacy default stream) and
+ *   returns after that work is enqueued unless stated otherwise.  Pointers documented
+ *   "host" are ordinary host memory.  The caller owns every buffer it passes; the
+ *   library keeps no pointer to caller memory after a call returns.
+ * - Return codes: 0 success; BIE_ENOCONV (+1) solver stopped before the tolerance (the
+ *   outputs hold the last iterate); negative values are errors (no output written),
+ *   with a message retrievable by bie_last_error() on the same thread.
+ * - A context is not thread safe: calls on one context must not overlap.
+ */
+#ifndef BIE_H
+#define BIE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BIE_OK 0
+#define BIE_ENOCONV 1
+#define BIE_EINVAL (-1)
+#define BIE_EOVERLAP (-2)
+#define BIE_EDEVICE (-3)
+#define BIE_ENOMEM (-4)
+
+/* Operators for bie_apply_bio.  Each is applied to a node density mu on all spheres.
+ * The layer potentials of sphere s at a node x of sphere t are evaluated by
+ *  - t == s: spectral self evaluation (Section 4.1, Eqs. 4.6-4.7): vector transform,
+ *    diagonal signature of Theorem 2 / Table 3.12, inverse transform; the double layer
+ *    is its principal value D_pv = D_+ - 1/2;
+ *  - t != s and |c_t - c_s| - 2 < near_gap (the separation test of Eq. 4.5): the
+ *    exterior formulas 3.6-3.11 on the source's vector-harmonic coefficients;
+ *  - otherwise: the smooth quadrature of Eq. 4.4 (all-pairs sum over source nodes). */
+#define BIE_OP_S 1        /* sum_k S_k[mu]                                             */
+#define BIE_OP_D 2        /* sum_k D_k[mu] (principal value on the own sphere)          */
+#define BIE_OP_SD_BIE 3   /* 1/2 mu + sum_k (S_k + D_k)[mu]          Eqs. 5.4 / 5.17     */
+#define BIE_OP_DN_BIE 4   /* 1/2 psi + sum_k (D_k + N_k)[psi]        Eq. 5.19; N_k is the
+                             Stokeslet + rotlet at c_k of strength int psi and torque
+                             int (y - c_k) x psi, each with the 1/(8 pi) of Eq. 2.19     */
+#define BIE_OP_MOBILITY 5 /* bordered Eq. 5.17 + Eq. 5.15 with applied force/torque:
+                             input [mu (3N); v (3 n_b); omega (3 n_b)], output
+                             [1/2 mu + sum (S+D) mu - v_i - omega_i x (x - c_i);
+                              (1/4pi) int_k mu;  (3/8pi) int_k (y - c_k) x mu]           */
+/* Stage selectors, OR-ed into op (testing and profiling; default = all stages). */
+#define BIE_STAGE_SELF 0x100 /* identity + self term (+ bordered rows for MOBILITY)      */
+#define BIE_STAGE_NEAR 0x200 /* near-pair series                                         */
+#define BIE_STAGE_FAR 0x400  /* far-field all-pairs quadrature (+ completion for DN)     */
+
+#define BIE_FP64 0  /* every stage in float64                                            */
+#define BIE_MIXED 1 /* transforms and far-field pair sums in float32 (accumulated in
+                       float32), near series and all vectors in float64                 */
+
+typedef struct bie_ctx bie_ctx;
+
+typedef struct {
+  int p;             /* SH order, 1 <= p <= 20                                           */
+  int n_phi;         /* azimuthal nodes; 0 selects 2p; must be even and >= 2p            */
+  double near_gap;   /* surface-gap threshold d* of Eq. 4.5; <= 0 selects 1.0            */
+  int device;        /* HIP device ordinal                                               */
+  void* hip_stream;  /* hipStream_t for all device work (NULL = default stream)          */
+} bie_opts;
+
+/* Builds the discretisation for n_spheres unit spheres (Eq. 4.2 grid, Legendre and
+ * Fourier tables, eigenvalue tables of Table 3.12, near-pair lists of Eq. 4.5) and
+ * uploads it to the device.  centres: host, n_spheres x 3 row-major.  Fails with
+ * BIE_EOVERLAP when two centres are closer than 2 (overlapping spheres), BIE_EINVAL
+ * on bad options, BIE_ENOMEM / BIE_EDEVICE on allocation or device errors.  Blocks
+ * until the upload completes.  *out is owned by the caller and released by bie_free. */
+int bie_build_spheres(const double* centres, int64_t n_spheres, const bie_opts* opts, bie_ctx** out);
+
+void bie_free(bie_ctx* ctx);
+
+/* Number of nodes N; number of spheres; P per sphere; mmax.  Host outputs. */
+int bie_sizes(const bie_ctx* ctx, int64_t* n_nodes, int64_t* n_spheres, int64_t* nodes_per_sphere, int64_t* mmax);
+
+/* Node coordinates (N x 3) and quadrature weights (N, Eq. 4.4) in ABI node order.
+ * Host outputs; either pointer may be NULL. */
+int bie_get_nodes(const bie_ctx* ctx, double* xyz, double* weights);
+
+/* Number of directed near pairs (t, s), and optionally the pairs themselves as
+ * 2 x count int64 (row 0 targets, row 1 sources) into a host buffer of that size. */
+int bie_near_pairs(const bie_ctx* ctx, int64_t* count, int64_t* pairs);
+
+/* One application of an operator (BIE_OP_*, optionally OR-ed with BIE_STAGE_* bits)
+ * in the given precision.  mu, u: device float64, length 3N (3N + 6 n_b for
+ * BIE_OP_MOBILITY); u is overwritten.  mu and u must not alias. */
+int bie_apply_bio(bie_ctx* ctx, int op, int precision, const double* mu, double* u);
+
+/* Forward vector transform (Section 2.1: the quadrature projection onto V, W, X, equal
+ * to Eqs. 2.7-2.14 on band-limited fields) of a node field mu (device, 3N float64) into
+ * coef (device float64): per sphere k, family f in (V, W, X), modes ordered by m
+ * (0..mmax) then n (m..p) - the ordering of Fig. 1 - as (re, im) pairs:
+ * coef[((k*3 + f) * ncoef + i) * 2 + {0,1}], ncoef = sum_{m=0}^{mmax} (p + 1 - m).
+ * Entries of W, X at n = 0 are zero.  Negative m follow from c_{n,-m} = conj(c_{n,m}). */
+int bie_vsh_forward(bie_ctx* ctx, int precision, const double* mu, double* coef);
+/* Inverse transform (Eqs. 2.15-2.17 / synthesis) of coef (layout above) into u (3N). */
+int bie_vsh_inverse(bie_ctx* ctx, int precision, const double* coef, double* u);
+
+/* Solver options.  The paper names no iterative method; the library uses restarted,
+ * right-preconditioned flexible GMRES with classical Gram-Schmidt twice (CGS2) in
+ * float64.  precision = BIE_MIXED runs iterative refinement: float64 residuals
+ * b - A x with a float64 matvec, inner GMRES on the correction with BIE_MIXED matvecs
+ * to relative tolerance inner_tol. */
+#define BIE_PC_NONE 0 /* no preconditioner                                             */
+#define BIE_PC_M0 1   /* exact inverse of every sphere's isolated self operator        */
+#define BIE_PC_MLP 2  /* M0 plus the learned close-pair coarse correction              */
+
+typedef struct {
+  double tol;        /* stop when ||b - A x||_2 <= tol ||b||_2 (true residual)         */
+  int restart;       /* Krylov dimension per cycle (<= 0 selects 100)                    */
+  int max_iter;      /* total inner iterations (<= 0 selects 1000)                      */
+  int precision;     /* BIE_FP64 or BIE_MIXED                                           */
+  int precond;       /* BIE_PC_*                                                        */
+  double inner_tol;  /* BIE_MIXED inner tolerance (<= 0 selects 1e-4)                   */
+} bie_solve_opts;
+
+typedef struct {
+  int iters;            /* GMRES iterations (all cycles, all refinement steps)          */
+  int outer_steps;      /* refinement steps (1 for BIE_FP64)                            */
+  int matvecs_fp64;
+  int matvecs_mixed;
+  int fallback_used;    /* 1 if the preconditioned solve stalled and was restarted plain */
+  double rel_residual;  /* final true relative residual                                */
+  double seconds;       /* wall time of the solve (device synchronised)                 */
+} bie_solve_info;
+
+/* Resistance problem (Problem 5, Eqs. 5.18-5.19): given rigid velocities v and angular
+ * velocities omega (host, n_b x 3), solve (1/2 I + sum (D_k + N_k)) psi = v_i +
+ * omega_i x (x - c_i) and return F_k = int psi, T_k = int (y - c_k) x psi (host,
+ * n_b x 3): the force and torque each particle exerts on the fluid (6 pi v and 8 pi
+ * omega for an isolated sphere).  psi: optional device output (3N), else NULL.
+ * Synchronises the stream.  info may be NULL. */
+int bie_solve_resistance(bie_ctx* ctx, const double* v, const double* omega, const bie_solve_opts* opts,
+                         double* F, double* T, double* psi, bie_solve_info* info);
+
+/* Mobility problem in the bordered second-kind form of Problem 4 (Eqs. 5.14-5.17) with
+ * the force/torque conditions of Eq. 5.15 set to the applied F_k, T_k (host, n_b x 3):
+ * unknowns mu, v_k, omega_k.  slip: optional device u_s (3N) of Eq. 5.14, else NULL.
+ * Returns v, omega (host, n_b x 3); mu: optional device output (3N).  Synchronises the
+ * stream.  info may be NULL. */
+int bie_solve_mobility(bie_ctx* ctx, const double* F, const double* T, const double* slip,
+                       const bie_solve_opts* opts, double* v, double* omega, double* mu, bie_solve_info* info);
+
+/* Thread-local message of the last error on this thread ("" if none). */
+const char* bie_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BIE_H */

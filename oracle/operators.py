@@ -69,11 +69,12 @@ class Operators:
         return self.vsh.forward(mu[self.g.sphere_nodes(k)])
 
     # ---- the three parts -----------------------------------------------------------
-    def self_part(self, mu, a_s, a_d):
+    def self_part(self, mu, a_s, a_d, spheres=None):
+        """Self term on every sphere (or only on `spheres`; other entries stay 0)."""
         mu, batch = self._as_batch(mu)
         lam = self.eigen_scale(a_s, a_d)[..., None]
         out = np.zeros_like(mu)
-        for k in range(self.g.nb):
+        for k in (range(self.g.nb) if spheres is None else spheres):
             sl = self.g.sphere_nodes(k)
             out[sl] = self.vsh.inverse(lam * self.vsh.forward(mu[sl]))
         return out if batch else out[..., 0]
@@ -167,7 +168,7 @@ class Operators:
         a_s, a_d, c_i, compl = OPS[op]
         mu_b, batch = self._as_batch(mu)
         tg = self._targets(targets)
-        out = self.self_part(mu_b, a_s, a_d)[tg]
+        out = self.self_part(mu_b, a_s, a_d, np.unique(self.g.sphere_of[tg]))[tg]
         out = out + c_i * mu_b[tg]
         out += self.near_part(mu_b, a_s, a_d, tg)
         out += self.far_part(mu_b, a_s, a_d, tg)

@@ -1,0 +1,317 @@
+// C ABI entry points (include/bie.h) and the matvec orchestration.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "bie_internal.h"
+
+namespace bie {
+void build(bie_ctx* c, const double* centres, int64_t nb, const bie_opts* o);
+const char* last_error();
+int solve(bie_ctx* c, int op, const double* b, double* x, int64_t n, const bie_solve_opts* so, bie_solve_info* info);
+
+// Table 3.12: S, D_+ eigenvalues per family (V, W, X) and degree n.
+static void eig_S(int n, double e[3]) {
+  const double d = n;
+  e[0] = d / ((2 * d + 1) * (2 * d + 3));
+  e[1] = n >= 1 ? (d + 1) / ((2 * d + 1) * (2 * d - 1)) : 0.0;
+  e[2] = n >= 1 ? 1.0 / (2 * d + 1) : 0.0;
+}
+static void eig_Dplus(int n, double e[3]) {
+  const double d = n;
+  e[0] = (2 * d * d + 4 * d + 3) / ((2 * d + 1) * (2 * d + 3));
+  e[1] = n >= 1 ? 2.0 * (d - 1) * (d + 1) / ((2 * d + 1) * (2 * d - 1)) : 0.0;
+  e[2] = n >= 1 ? (d - 1) / (2 * d + 1) : 0.0;
+}
+
+// Self-term multipliers a_S lambda_S + a_D lambda_Dpv (D_pv = D_+ - 1/2, jump A.7).
+static void self_lambda(const OpSpec& s, int p, double lam[3][33]) {
+  for (int n = 0; n <= p; ++n) {
+    double es[3], ed[3];
+    eig_S(n, es);
+    eig_Dplus(n, ed);
+    for (int f = 0; f < 3; ++f) {
+      const bool exists = (f == 0) || n >= 1;
+      lam[f][n] = exists ? s.a_s * es[f] + s.a_d * (ed[f] - 0.5) : 0.0;
+    }
+  }
+}
+
+void apply(bie_ctx* c, int op, int precision, const double* mu, double* u) {
+  const int base = op & 0xff;
+  int stages = op & (BIE_STAGE_SELF | BIE_STAGE_NEAR | BIE_STAGE_FAR);
+  if (stages == 0) stages = BIE_STAGE_SELF | BIE_STAGE_NEAR | BIE_STAGE_FAR;
+  if (precision != BIE_FP64 && precision != BIE_MIXED) throw Error{BIE_EINVAL, "bad precision"};
+  const OpSpec spec = op_spec(base);
+  VshCall v;
+  v.mu = mu;
+  v.u = u;
+  v.write_q = (stages & BIE_STAGE_FAR) != 0;
+  v.write_coef = (stages & BIE_STAGE_NEAR) != 0 && !c->near_idx.empty();
+  v.do_self = (stages & BIE_STAGE_SELF) != 0;
+  v.want_moments = spec.completion && (stages & BIE_STAGE_FAR);
+  v.bordered = spec.bordered;
+  v.c_identity = spec.c_identity;
+  self_lambda(spec, c->p, v.lam);
+  launch_vsh(c, precision, v);
+  if (stages & BIE_STAGE_NEAR) launch_near(c, spec, u);
+  if (stages & BIE_STAGE_FAR) launch_far(c, precision, spec, u);
+}
+
+// Block-diagonal preconditioner M0: the exact inverse of every sphere's isolated self
+// operator.  On the band-limited part it is diagonal in V, W, X (Theorem 2); on the
+// grid complement the operator is 1/2 I, so M0 = 2 I + Pi^+ (Lambda^-1 - 2) Pi.
+//  - resistance form 1/2 + D_pv + N: D_+ vanishes on W_1, X_1 and the completion flow
+//    maps W_1[a] -> 2/3 W_1[a] - 1/6 V_1[a], X_1 -> 1/3 X_1 (V_1 and higher modes carry
+//    no force or torque), so the degree-one block inverse is
+//    V_1: 5/3, W_1: 3/2 with V'_1 += 5/12 W_1, X_1: 3; elsewhere 1 / D_+.
+//  - mobility form 1/2 + S + D_pv = S + D_+ ((n+1)/(2n+1) on V, W; n/(2n+1) on X),
+//    plus the rigid-body rows solved in closed form (see the transform kernel).
+void dev_precond_m0(bie_ctx* c, int op_base, int precision, const double* r, double* z) {
+  VshCall v;
+  v.mu = r;
+  v.u = z;
+  v.do_self = true;
+  v.c_identity = 2.0;
+  for (int n = 0; n <= c->p; ++n) {
+    double es[3], ed[3];
+    eig_S(n, es);
+    eig_Dplus(n, ed);
+    for (int f = 0; f < 3; ++f) {
+      const bool exists = (f == 0) || n >= 1;
+      double inv = 0.0;
+      if (exists) {
+        if (op_base == BIE_OP_DN_BIE) {
+          if (n == 1 && f == 0) inv = 5.0 / 3.0;
+          else if (n == 1 && f == 1) inv = 1.5;
+          else if (n == 1 && f == 2) inv = 3.0;
+          else inv = 1.0 / ed[f];
+        } else {
+          inv = 1.0 / (es[f] + ed[f]);
+        }
+      }
+      v.lam[f][n] = exists ? inv - 2.0 : 0.0;
+    }
+  }
+  if (op_base == BIE_OP_DN_BIE) v.wv1 = 5.0 / 12.0;
+  if (op_base == BIE_OP_MOBILITY) v.pc_border = true;
+  launch_vsh(c, precision, v);
+}
+
+}  // namespace bie
+
+using bie::Error;
+
+#define BIE_TRY(...)                               \
+  try {                                            \
+    bie::clear_error();                            \
+    __VA_ARGS__;                                   \
+  } catch (const Error& e) {                       \
+    bie::set_error(e.msg);                         \
+    return e.code;                                 \
+  } catch (const std::bad_alloc&) {                \
+    bie::set_error("host allocation failed");      \
+    return BIE_ENOMEM;                             \
+  } catch (const std::exception& e) {              \
+    bie::set_error(e.what());                      \
+    return BIE_EINVAL;                             \
+  }
+
+extern "C" {
+
+int bie_build_spheres(const double* centres, int64_t n_spheres, const bie_opts* opts, bie_ctx** out) {
+  if (!out) {
+    bie::set_error("out is NULL");
+    return BIE_EINVAL;
+  }
+  *out = nullptr;
+  bie_ctx* c = new (std::nothrow) bie_ctx();
+  if (!c) return BIE_ENOMEM;
+  try {
+    bie::clear_error();
+    bie::build(c, centres, n_spheres, opts);
+  } catch (const Error& e) {
+    bie::set_error(e.msg);
+    bie_free(c);
+    return e.code;
+  } catch (const std::exception& e) {
+    bie::set_error(e.what());
+    bie_free(c);
+    return BIE_EINVAL;
+  }
+  *out = c;
+  return BIE_OK;
+}
+
+void bie_free(bie_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  bie::DevBuf* bufs[] = {&c->centres4, &c->excl, &c->dnear_ptr, &c->dnear_idx, &c->otab, &c->otab_f, &c->frame,
+                         &c->wnode, &c->leg, &c->leg_f, &c->dft, &c->dft_f, &c->wlat_d, &c->wlat_f, &c->modes,
+                         &c->rec, &c->coef, &c->q, &c->partial, &c->moments, &c->scal, &c->krylov, &c->zbasis,
+                         &c->vec[0], &c->vec[1], &c->vec[2], &c->vec[3], &c->vec[4], &c->vec[5]};
+  for (auto* b : bufs) b->release();
+  delete c;
+}
+
+int bie_sizes(const bie_ctx* c, int64_t* n_nodes, int64_t* n_spheres, int64_t* nodes_per_sphere, int64_t* mmax) {
+  if (!c) return BIE_EINVAL;
+  if (n_nodes) *n_nodes = c->N;
+  if (n_spheres) *n_spheres = c->nb;
+  if (nodes_per_sphere) *nodes_per_sphere = c->P;
+  if (mmax) *mmax = c->mmax;
+  return BIE_OK;
+}
+
+int bie_get_nodes(const bie_ctx* c, double* xyz, double* w) {
+  if (!c) return BIE_EINVAL;
+  for (int64_t k = 0; k < c->nb; ++k)
+    for (int j = 0; j < c->nlat; ++j) {
+      const double tj = c->t[j], sj = std::sqrt(std::max(0.0, 1.0 - tj * tj));
+      for (int l = 0; l < c->n_phi; ++l) {
+        const int64_t g = k * c->P + j * c->n_phi + l;
+        if (xyz) {
+          xyz[3 * g] = c->centres[3 * k] + sj * std::cos(c->phi[l]);
+          xyz[3 * g + 1] = c->centres[3 * k + 1] + sj * std::sin(c->phi[l]);
+          xyz[3 * g + 2] = c->centres[3 * k + 2] + tj;
+        }
+        if (w) w[g] = c->wlat[j];
+      }
+    }
+  return BIE_OK;
+}
+
+int bie_near_pairs(const bie_ctx* c, int64_t* count, int64_t* pairs) {
+  if (!c || !count) return BIE_EINVAL;
+  *count = (int64_t)c->near_idx.size();
+  if (pairs) {
+    int64_t e = 0;
+    for (int64_t t = 0; t < c->nb; ++t)
+      for (int i = c->near_ptr[t]; i < c->near_ptr[t + 1]; ++i, ++e) {
+        pairs[e] = t;
+        pairs[*count + e] = c->near_idx[i];
+      }
+  }
+  return BIE_OK;
+}
+
+int bie_apply_bio(bie_ctx* c, int op, int precision, const double* mu, double* u) {
+  if (!c || !mu || !u) {
+    bie::set_error("null argument");
+    return BIE_EINVAL;
+  }
+  if (mu == u) {
+    bie::set_error("mu and u alias");
+    return BIE_EINVAL;
+  }
+  BIE_TRY(bie::apply(c, op, precision, mu, u));
+  return BIE_OK;
+}
+
+int bie_vsh_forward(bie_ctx* c, int precision, const double* mu, double* coef) {
+  if (!c || !mu || !coef) return BIE_EINVAL;
+  BIE_TRY({
+    bie::VshCall v;
+    v.mu = mu;
+    v.write_coef = true;
+    bie::launch_vsh(c, precision, v);
+    BIE_HIP(hipMemcpyAsync(coef, c->coef.ptr, (size_t)c->nb * 3 * c->ncoef * 2 * sizeof(double),
+                           hipMemcpyDeviceToDevice, c->stream));
+  });
+  return BIE_OK;
+}
+
+int bie_vsh_inverse(bie_ctx* c, int precision, const double* coef, double* u) {
+  if (!c || !coef || !u) return BIE_EINVAL;
+  BIE_TRY({
+    bie::VshCall v;
+    v.coef_in = coef;
+    v.coef_is_input = true;
+    v.u = u;
+    bie::launch_vsh(c, precision, v);
+  });
+  return BIE_OK;
+}
+
+int bie_solve_resistance(bie_ctx* c, const double* v, const double* omega, const bie_solve_opts* opts, double* F,
+                         double* T, double* psi, bie_solve_info* info) {
+  if (!c || !v || !omega || !F || !T) {
+    bie::set_error("null argument");
+    return BIE_EINVAL;
+  }
+  int rc = BIE_OK;
+  BIE_TRY({
+    const int64_t n = 3 * c->N;
+    bie::DevBuf rhs, x, vw;
+    rhs.alloc(n * sizeof(double));
+    x.alloc(n * sizeof(double));
+    vw.alloc(6 * c->nb * sizeof(double));
+    BIE_HIP(hipMemcpyAsync(vw.ptr, v, 3 * c->nb * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    BIE_HIP(hipMemcpyAsync(vw.as<double>() + 3 * c->nb, omega, 3 * c->nb * sizeof(double), hipMemcpyHostToDevice,
+                           c->stream));
+    bie::dev_rigid_rhs(c, vw.as<double>(), vw.as<double>() + 3 * c->nb, rhs.as<double>());
+    rc = bie::solve(c, BIE_OP_DN_BIE, rhs.as<double>(), x.as<double>(), n, opts, info);
+    // F_k = int psi, T_k = int (y - c_k) x psi
+    bie::VshCall m;
+    m.mu = x.as<double>();
+    m.want_moments = true;
+    bie::launch_vsh(c, BIE_FP64, m);
+    std::vector<double> mom(6 * c->nb);
+    BIE_HIP(hipMemcpyAsync(mom.data(), c->moments.ptr, mom.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (psi) BIE_HIP(hipMemcpyAsync(psi, x.ptr, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    BIE_HIP(hipStreamSynchronize(c->stream));
+    for (int64_t k = 0; k < c->nb; ++k)
+      for (int d = 0; d < 3; ++d) {
+        F[3 * k + d] = mom[6 * k + d];
+        T[3 * k + d] = mom[6 * k + 3 + d];
+      }
+    rhs.release();
+    x.release();
+    vw.release();
+  });
+  return rc;
+}
+
+int bie_solve_mobility(bie_ctx* c, const double* F, const double* T, const double* slip, const bie_solve_opts* opts,
+                       double* v, double* omega, double* mu, bie_solve_info* info) {
+  if (!c || !F || !T || !v || !omega) {
+    bie::set_error("null argument");
+    return BIE_EINVAL;
+  }
+  int rc = BIE_OK;
+  BIE_TRY({
+    const int64_t n3 = 3 * c->N, n = n3 + 6 * c->nb;
+    bie::DevBuf rhs, x;
+    rhs.alloc(n * sizeof(double));
+    x.alloc(n * sizeof(double));
+    if (slip)
+      BIE_HIP(hipMemcpyAsync(rhs.ptr, slip, n3 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    else
+      bie::dev_fill(c, rhs.as<double>(), 0.0, n3);
+    std::vector<double> tail(6 * c->nb);
+    for (int64_t k = 0; k < 3 * c->nb; ++k) {
+      tail[k] = F[k] / (4.0 * M_PI);
+      tail[3 * c->nb + k] = 3.0 * T[k] / (8.0 * M_PI);
+    }
+    BIE_HIP(hipMemcpyAsync(rhs.as<double>() + n3, tail.data(), tail.size() * sizeof(double), hipMemcpyHostToDevice,
+                           c->stream));
+    rc = bie::solve(c, BIE_OP_MOBILITY, rhs.as<double>(), x.as<double>(), n, opts, info);
+    std::vector<double> out(6 * c->nb);
+    BIE_HIP(hipMemcpyAsync(out.data(), x.as<double>() + n3, out.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+    if (mu) BIE_HIP(hipMemcpyAsync(mu, x.ptr, n3 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    BIE_HIP(hipStreamSynchronize(c->stream));
+    for (int64_t k = 0; k < 3 * c->nb; ++k) {
+      v[k] = out[k];
+      omega[k] = out[3 * c->nb + k];
+    }
+    rhs.release();
+    x.release();
+  });
+  return rc;
+}
+
+const char* bie_last_error(void) { return bie::last_error(); }
+
+}  // extern "C"

@@ -1,0 +1,125 @@
+// Internal declarations of the MI355X sphere-BIE library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "bie.h"
+
+namespace bie {
+
+// Thread-local error text behind bie_last_error().
+void set_error(const std::string& msg);
+void clear_error();
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define BIE_HIP(call)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      throw ::bie::Error{BIE_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)};    \
+  } while (0)
+
+// Device buffer owned by a context.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void alloc(size_t n);
+  void release();
+  template <typename T>
+  T* as() const { return static_cast<T*>(ptr); }
+};
+
+// Per-operator constants of the layer-potential combination a_S S + a_D D.
+struct OpSpec {
+  double a_s, a_d, c_identity;
+  bool completion, bordered;
+};
+OpSpec op_spec(int op_base);
+
+}  // namespace bie
+
+struct bie_ctx {
+  // discretisation
+  int p = 0, n_phi = 0, mmax = 0, P = 0, ncoef = 0, nlat = 0;
+  int64_t nb = 0, N = 0;
+  double near_gap = 1.0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+
+  // host copies
+  std::vector<double> centres;  // nb x 3
+  std::vector<double> t, lam, theta, wlat, phi;
+  std::vector<int> near_ptr, near_idx;  // CSR, target sphere -> near source spheres
+  std::vector<int> coef_m, coef_n, coef_off;  // mode (m, n) of each coefficient slot; slot of (m, m)
+
+  // device: geometry
+  bie::DevBuf centres4;   // nb x 4 double (x, y, z, 0)
+  bie::DevBuf excl;       // nb x nwords uint32: bit s of row t set if s == t or (t, s) near
+  int nwords = 0;
+  bie::DevBuf dnear_ptr, dnear_idx;
+  bie::DevBuf otab, otab_f;    // P x 4 unit offsets of the nodes of a sphere (double / float)
+  bie::DevBuf frame;           // P x 9 double: e_r, e_theta, e_phi at each node
+  bie::DevBuf wnode;           // P double: quadrature weight of each node of a sphere
+  // device: transform tables, double and float copies
+  bie::DevBuf leg, leg_f;      // 3 x ncoef x nlat: Pbar, dPbar/dtheta, m Pbar / sin(theta)
+  bie::DevBuf dft, dft_f;      // (mmax+1) x n_phi x 2: cos(m phi_l), sin(m phi_l)
+  bie::DevBuf wlat_d, wlat_f;  // nlat latitude weights
+  bie::DevBuf modes;           // ncoef x 2 int: (m, n)
+  bie::DevBuf rec;             // ncoef x 6 double: Legendre recurrence constants (near series)
+  // device: per-call work
+  bie::DevBuf coef;            // nb x 3 x ncoef x 2 double: raw coefficients (near series input)
+  bie::DevBuf q;               // N x 4 (double): far-field source strengths w * mu
+  bie::DevBuf partial;         // nsplit x N x 3 double: far-field partial sums
+  bie::DevBuf moments;         // nb x 6 double: int mu, int (y - c) x mu
+  bie::DevBuf scal;            // small scratch for reductions
+  int nsplit = 1;
+
+  // solver work space (allocated on first solve)
+  bie::DevBuf krylov, zbasis, vec[6];
+  int krylov_cols = 0;
+  int64_t krylov_n = 0;
+};
+
+namespace bie {
+// One launch of the per-sphere transform kernel (vsh.hip).
+struct VshCall {
+  const double* mu = nullptr;       // node field input (3N, or 3N + 6 n_b when bordered)
+  const double* coef_in = nullptr;  // coefficient input (coef_is_input)
+  double* u = nullptr;              // node field output
+  bool write_q = false;             // far-field source strengths w * mu -> ctx->q
+  bool write_coef = false;          // raw V, W, X coefficients -> ctx->coef
+  bool do_self = false;             // synthesise lam * coefficients (+ identity term)
+  bool want_moments = false;        // int mu, int o x mu -> ctx->moments
+  bool coef_is_input = false;
+  bool bordered = false;            // mobility matvec rows
+  bool pc_border = false;           // mobility block preconditioner rows
+  double c_identity = 0.0, scale_out = 1.0, wv1 = 0.0;
+  double lam[3][33] = {};
+};
+void launch_vsh(bie_ctx* c, int precision, const VshCall& v);
+void launch_near(bie_ctx* c, const OpSpec& spec, double* u);
+void launch_far(bie_ctx* c, int precision, const OpSpec& spec, double* u);
+void apply(bie_ctx* c, int op, int precision, const double* mu, double* u);
+
+// Small BLAS-1 helpers on device vectors (float64), stream-ordered on c->stream.
+void dev_dot_many(bie_ctx* c, const double* V, int64_t ld, int k, const double* w, int64_t n, double* host_out);
+void dev_gemv_sub(bie_ctx* c, const double* V, int64_t ld, int k, const double* h_host, double* w, int64_t n);
+void dev_axpby(bie_ctx* c, double a, const double* x, double b, double* y, int64_t n);  // y = a x + b y
+void dev_copy(bie_ctx* c, const double* x, double* y, int64_t n);
+void dev_fill(bie_ctx* c, double* y, double v, int64_t n);
+double dev_norm(bie_ctx* c, const double* x, int64_t n);
+void dev_rigid_rhs(bie_ctx* c, const double* v_dev, const double* om_dev, double* b);
+void dev_precond_m0(bie_ctx* c, int op_base, int precision, const double* r, double* z);
+}  // namespace bie

@@ -1,0 +1,245 @@
+// Far-field smooth quadrature (Eq. 4.4): all-pairs Stokeslet / double-layer sums over the
+// nodes of every well-separated sphere pair (Eq. 4.5), the stage the paper hands to an
+// FMM (Section 4.3).  Here it is a tiled direct sum on the GPU.
+//
+// Work decomposition: a work-group owns 256 x TPL target nodes and one contiguous range
+// of source spheres (grid.y splits the spheres so that the launch has thousands of
+// work-groups).  Sources are staged in LDS one sphere at a time: the unit offsets of a
+// sphere's nodes (the same table for every sphere, loaded once) and the strengths
+// q = w mu of the current sphere.  All lanes read the same LDS word per source
+// (broadcast).  For each (target, source sphere) the target position relative to the
+// source centre is formed from the float64 centre difference plus the target's own
+// offset, so float32 pair arithmetic keeps full relative accuracy at any box size.
+// Self and near source spheres are skipped through a per-target bit mask (a whole wave
+// skips when all its lanes are excluded); partial sums over one source sphere are
+// added to the running total with Kahan compensation in float32.
+// The completion flow of the resistance problem (Stokeslet + rotlet at every centre,
+// Eqs. 5.18-5.19) rides along once per (target, sphere) in float64.
+#include "bie_internal.h"
+
+namespace bie {
+
+struct FarParams {
+  const void* q;          // N x 4 (R): w * mu
+  const void* otab;       // P x 4 (R): unit offsets of the nodes of a sphere
+  const double* centres4; // nb x 4
+  const uint32_t* excl;   // nb x nwords
+  const double* moments;  // nb x 6 (completion only)
+  double* partial;        // nsplit x N x 3
+  int64_t N, nb;
+  int P, nwords, sph_per_split, completion;
+  double cscale;          // kernel constant applied to the pair sums
+};
+
+template <typename R>
+__device__ __forceinline__ R rsqrt_r(R x);
+template <>
+__device__ __forceinline__ float rsqrt_r<float>(float x) {
+  return __builtin_amdgcn_rsqf(x);
+}
+template <>
+__device__ __forceinline__ double rsqrt_r<double>(double x) {
+  // hardware estimate refined by two Newton steps y <- y (3 - x y^2) / 2
+  double y = __builtin_amdgcn_rsq(x);
+  double h = x * y;
+  double e = fma(-h, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  h = x * y;
+  e = fma(-h, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  return y;
+}
+
+// KIND: 1 = Stokeslet, 2 = double layer, 3 = Stokeslet + double layer (ratio 6 : 1 after
+// the 1/(8 pi) factor is taken out).
+template <typename R, int KIND>
+__device__ __forceinline__ void pair(const R xr, const R yr, const R zr, const R ox, const R oy, const R oz,
+                                     const R qx, const R qy, const R qz, R& ax, R& ay, R& az) {
+  const R rx = xr - ox, ry = yr - oy, rz = zr - oz;
+  const R r2 = rx * rx + ry * ry + rz * rz;
+  const R ir = rsqrt_r<R>(r2);
+  const R ir2 = ir * ir;
+  const R rq = rx * qx + ry * qy + rz * qz;
+  if (KIND == 1) {
+    const R c = rq * ir2 * ir;
+    ax += qx * ir + rx * c;
+    ay += qy * ir + ry * c;
+    az += qz * ir + rz * c;
+  } else if (KIND == 2) {
+    const R rn = rx * ox + ry * oy + rz * oz;
+    const R c = rq * rn * (ir2 * ir2 * ir);
+    ax += rx * c;
+    ay += ry * c;
+    az += rz * c;
+  } else {
+    const R rn = rx * ox + ry * oy + rz * oz;
+    const R t = (R)1 + (R)6 * rn * ir2;
+    const R c = rq * ir2 * ir * t;
+    ax += qx * ir + rx * c;
+    ay += qy * ir + ry * c;
+    az += qz * ir + rz * c;
+  }
+}
+
+template <typename R>
+struct R4 {
+  R x, y, z, w;
+};
+
+template <typename R, int KIND, int TPL>
+__global__ __launch_bounds__(256) void far_kernel(FarParams a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R4<R>* ot = reinterpret_cast<R4<R>*>(smem_raw);
+  R4<R>* qs = ot + a.P;
+  const int tid = threadIdx.x;
+  const int P = a.P;
+  const R4<R>* qg = reinterpret_cast<const R4<R>*>(a.q);
+  const R4<R>* og = reinterpret_cast<const R4<R>*>(a.otab);
+  for (int i = tid; i < P; i += 256) ot[i] = og[i];
+
+  const int s_begin = blockIdx.y * a.sph_per_split;
+  const int s_end = (int)min<int64_t>(a.nb, (int64_t)s_begin + a.sph_per_split);
+
+  int64_t g[TPL];
+  int tsph[TPL];
+  bool valid[TPL];
+  double ct[TPL][3];
+  R oxt[TPL][3];
+  R tot[TPL][3], comp[TPL][3];
+  double cpl[TPL][3];
+#pragma unroll
+  for (int k = 0; k < TPL; ++k) {
+    g[k] = (int64_t)blockIdx.x * 256 * TPL + k * 256 + tid;
+    valid[k] = g[k] < a.N;
+    const int64_t gg = valid[k] ? g[k] : 0;
+    tsph[k] = (int)(gg / P);
+    const int li = (int)(gg - (int64_t)tsph[k] * P);
+    for (int d = 0; d < 3; ++d) {
+      ct[k][d] = a.centres4[4 * tsph[k] + d];
+      tot[k][d] = 0;
+      comp[k][d] = 0;
+      cpl[k][d] = 0.0;
+    }
+    const R4<R> o = og[li];
+    oxt[k][0] = o.x;
+    oxt[k][1] = o.y;
+    oxt[k][2] = o.z;
+  }
+
+  for (int s = s_begin; s < s_end; ++s) {
+    __syncthreads();
+    for (int i = tid; i < P; i += 256) qs[i] = qg[(int64_t)s * P + i];
+    const double csx = a.centres4[4 * s], csy = a.centres4[4 * s + 1], csz = a.centres4[4 * s + 2];
+    R xr[TPL], yr[TPL], zr[TPL];
+    bool skip[TPL];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+      const uint32_t bits = a.excl[(int64_t)tsph[k] * a.nwords + (s >> 5)];
+      skip[k] = !valid[k] || ((bits >> (s & 31)) & 1u);
+      const double dx = ct[k][0] - csx, dy = ct[k][1] - csy, dz = ct[k][2] - csz;
+      xr[k] = (R)dx + oxt[k][0];
+      yr[k] = (R)dy + oxt[k][1];
+      zr[k] = (R)dz + oxt[k][2];
+      any = any || !skip[k];
+      if (a.completion && valid[k]) {
+        // Stokeslet of strength F_s and rotlet of torque T_s at c_s, in float64
+        const double px = dx + (double)oxt[k][0], py = dy + (double)oxt[k][1], pz = dz + (double)oxt[k][2];
+        const double* mo = a.moments + 6 * (int64_t)s;
+        const double r2 = px * px + py * py + pz * pz;
+        const double ir = 1.0 / sqrt(r2);
+        const double ir3 = ir * ir * ir;
+        const double rf = px * mo[0] + py * mo[1] + pz * mo[2];
+        cpl[k][0] += mo[0] * ir + px * rf * ir3 + (mo[4] * pz - mo[5] * py) * ir3;
+        cpl[k][1] += mo[1] * ir + py * rf * ir3 + (mo[5] * px - mo[3] * pz) * ir3;
+        cpl[k][2] += mo[2] * ir + pz * rf * ir3 + (mo[3] * py - mo[4] * px) * ir3;
+      }
+    }
+    __syncthreads();
+    // skip the sphere when every lane of the wave excludes it (self / near / padding)
+    if (__any(any ? 1 : 0) == 0) continue;
+    R acc[TPL][3];
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) acc[k][0] = acc[k][1] = acc[k][2] = 0;
+    for (int i = 0; i < P; ++i) {
+      const R4<R> o = ot[i];
+      const R4<R> qq = qs[i];
+#pragma unroll
+      for (int k = 0; k < TPL; ++k)
+        pair<R, KIND>(xr[k], yr[k], zr[k], o.x, o.y, o.z, qq.x, qq.y, qq.z, acc[k][0], acc[k][1], acc[k][2]);
+    }
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+      if (skip[k]) continue;
+      for (int d = 0; d < 3; ++d) {
+        // Kahan-compensated accumulation of the per-sphere partial sum
+        const R y = acc[k][d] - comp[k][d];
+        const R tt = tot[k][d] + y;
+        comp[k][d] = (tt - tot[k][d]) - y;
+        tot[k][d] = tt;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < TPL; ++k) {
+    if (!valid[k]) continue;
+    double* out = a.partial + ((int64_t)blockIdx.y * a.N + g[k]) * 3;
+    for (int d = 0; d < 3; ++d)
+      out[d] = a.cscale * ((double)tot[k][d] - (double)comp[k][d]) + (1.0 / (8.0 * M_PI)) * cpl[k][d];
+  }
+}
+
+__global__ void reduce_partials(const double* partial, int nsplit, int64_t n3, double* u) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n3; i += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < nsplit; ++k) s += partial[(int64_t)k * n3 + i];
+    u[i] += s;
+  }
+}
+
+template <typename R, int KIND>
+static void far_launch(bie_ctx* c, const FarParams& a, dim3 grid) {
+  constexpr int TPL = 2;
+  const size_t sm = 2 * (size_t)c->P * sizeof(R4<R>);
+  far_kernel<R, KIND, TPL><<<grid, dim3(256), sm, c->stream>>>(a);
+}
+
+void launch_far(bie_ctx* c, int precision, const OpSpec& spec, double* u) {
+  constexpr int TPL = 2;
+  FarParams a{};
+  const bool f32 = precision == BIE_MIXED;
+  a.q = c->q.ptr;
+  a.otab = f32 ? c->otab_f.ptr : c->otab.ptr;
+  a.centres4 = c->centres4.as<double>();
+  a.excl = c->excl.as<uint32_t>();
+  a.moments = c->moments.as<double>();
+  a.partial = c->partial.as<double>();
+  a.N = c->N;
+  a.nb = c->nb;
+  a.P = c->P;
+  a.nwords = c->nwords;
+  a.sph_per_split = (int)((c->nb + c->nsplit - 1) / c->nsplit);
+  a.completion = spec.completion ? 1 : 0;
+  const int nsplit = (int)((c->nb + a.sph_per_split - 1) / a.sph_per_split);
+  const int kind = (spec.a_s != 0.0 ? 1 : 0) + (spec.a_d != 0.0 ? 2 : 0);
+  // S: 1/(8 pi) (q/r + r (r.q)/r^3); D: 3/(4 pi) r (r.q)(r.n)/r^5; S+D: 1/(8 pi) [...]
+  a.cscale = (kind == 2) ? 3.0 / (4.0 * M_PI) : 1.0 / (8.0 * M_PI);
+  dim3 grid((unsigned)((c->N + 256 * TPL - 1) / (256 * TPL)), (unsigned)nsplit);
+  if (kind == 0) throw Error{BIE_EINVAL, "empty far-field kernel"};
+  if (f32) {
+    if (kind == 1) far_launch<float, 1>(c, a, grid);
+    if (kind == 2) far_launch<float, 2>(c, a, grid);
+    if (kind == 3) far_launch<float, 3>(c, a, grid);
+  } else {
+    if (kind == 1) far_launch<double, 1>(c, a, grid);
+    if (kind == 2) far_launch<double, 2>(c, a, grid);
+    if (kind == 3) far_launch<double, 3>(c, a, grid);
+  }
+  BIE_HIP(hipGetLastError());
+  const int64_t n3 = 3 * c->N;
+  const int blocks = (int)std::min<int64_t>((n3 + 255) / 256, 4096);
+  reduce_partials<<<dim3(blocks), dim3(256), 0, c->stream>>>(c->partial.as<double>(), nsplit, n3, u);
+  BIE_HIP(hipGetLastError());
+}
+
+}  // namespace bie

@@ -1,0 +1,347 @@
+// Host-side set-up of the discretisation (Section 4: grid of Eq. 4.2, weights of Eq. 4.4,
+// near-pair classification of Eq. 4.5) and the tables the kernels read.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <unordered_map>
+
+#include "bie_internal.h"
+
+namespace bie {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+void clear_error() { g_err.clear(); }
+const char* last_error() { return g_err.c_str(); }
+
+void DevBuf::alloc(size_t n) {
+  release();
+  if (n == 0) n = 16;
+  hipError_t e = hipMalloc(&ptr, n);
+  if (e != hipSuccess) {
+    ptr = nullptr;
+    throw Error{BIE_ENOMEM, std::string("hipMalloc(") + std::to_string(n) + "): " + hipGetErrorString(e)};
+  }
+  bytes = n;
+}
+void DevBuf::release() {
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  bytes = 0;
+}
+
+OpSpec op_spec(int op_base) {
+  switch (op_base) {
+    case BIE_OP_S: return {1.0, 0.0, 0.0, false, false};
+    case BIE_OP_D: return {0.0, 1.0, 0.0, false, false};
+    case BIE_OP_SD_BIE: return {1.0, 1.0, 0.5, false, false};
+    case BIE_OP_DN_BIE: return {0.0, 1.0, 0.5, true, false};
+    case BIE_OP_MOBILITY: return {1.0, 1.0, 0.5, false, true};
+    default: throw Error{BIE_EINVAL, "unknown operator " + std::to_string(op_base)};
+  }
+}
+
+// Gauss-Legendre nodes (descending) and weights on [-1, 1] by Newton's method on
+// P_n, with the three-term recurrence for P_n and its derivative.
+static void gauss_legendre(int n, std::vector<double>& t, std::vector<double>& w) {
+  t.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double x = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      double pn = (n == 1) ? x : p1;
+      double pm = (n == 1) ? 1.0 : p0;
+      dp = n * (x * pn - pm) / (x * x - 1.0);
+      double dx = pn / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16 && it > 2) break;
+    }
+    t[i] = x;
+    w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+}
+
+// Normalised associated Legendre functions without the Condon-Shortley phase
+// (Eq. 2.1) at t = cos(theta), s = sin(theta) > 0, for 0 <= m <= mmax, m <= n <= nmax:
+//   Pbar_0^0 = 1/sqrt(4 pi), Pbar_m^m = sqrt((2m+1)/(2m)) s Pbar_{m-1}^{m-1},
+//   Pbar_{m+1}^m = sqrt(2m+3) t Pbar_m^m,
+//   Pbar_n^m = a_nm (t Pbar_{n-1}^m - b_nm Pbar_{n-2}^m).
+// Q_n^m = Pbar_n^m / s obeys the same recurrence in n.  out[m][n].
+static void legendre_column(int m, int nmax, double t, double s, std::vector<double>& pm, std::vector<double>& qm) {
+  pm.assign(nmax + 2, 0.0);
+  qm.assign(nmax + 2, 0.0);
+  double pmm = 1.0 / std::sqrt(4.0 * M_PI), qmm = 0.0;
+  for (int k = 1; k <= m; ++k) {
+    double f = std::sqrt((2.0 * k + 1.0) / (2.0 * k));
+    qmm = f * pmm;  // Pbar_k^k / s
+    pmm = f * s * pmm;
+  }
+  if (m > nmax + 1) return;
+  pm[m] = pmm;
+  qm[m] = qmm;
+  if (m + 1 <= nmax + 1) {
+    pm[m + 1] = std::sqrt(2.0 * m + 3.0) * t * pmm;
+    qm[m + 1] = std::sqrt(2.0 * m + 3.0) * t * qmm;
+  }
+  for (int n = m + 2; n <= nmax + 1; ++n) {
+    double a = std::sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)m * m));
+    double b = std::sqrt(((n - 1.0) * (n - 1.0) - (double)m * m) / (4.0 * (n - 1.0) * (n - 1.0) - 1.0));
+    pm[n] = a * (t * pm[n - 1] - b * pm[n - 2]);
+    qm[n] = a * (t * qm[n - 1] - b * qm[n - 2]);
+  }
+}
+
+static double alpha_nm(int n, int m) {
+  return std::sqrt((double)n * n * ((n + 1.0) * (n + 1.0) - (double)m * m) / ((2.0 * n + 1.0) * (2.0 * n + 3.0)));
+}
+static double beta_nm(int n, int m) {
+  return std::sqrt((n + 1.0) * (n + 1.0) * ((double)n * n - (double)m * m) / ((2.0 * n + 1.0) * (2.0 * n - 1.0)));
+}
+
+// Table at one latitude: Pbar_n^m, dPbar_n^m/dtheta, m Pbar_n^m / sin(theta).
+// dPbar/dtheta uses sin(theta) dY_n/dtheta = alpha_n^m Y_{n+1} - beta_n^m Y_{n-1}
+// (the Legendre recurrence behind Eq. 2.9) for m >= 1 and dPbar_n^0/dtheta =
+// -sqrt(n(n+1)) Pbar_n^1 for m = 0.
+void legendre_tables(int p, int mmax, double t, double s, const std::vector<int>& cm, const std::vector<int>& cn,
+                     double* outP, double* outD, double* outQ) {
+  std::vector<double> pm, qm, p1, q1;
+  legendre_column(1, p, t, s, p1, q1);
+  for (int m = 0; m <= mmax; ++m) {
+    legendre_column(m, p, t, s, pm, qm);
+    for (size_t i = 0; i < cm.size(); ++i) {
+      if (cm[i] != m) continue;
+      int n = cn[i];
+      outP[i] = pm[n];
+      if (m == 0) {
+        outD[i] = -std::sqrt((double)n * (n + 1.0)) * p1[n];
+        outQ[i] = 0.0;
+      } else {
+        outD[i] = alpha_nm(n, m) * qm[n + 1] - (n >= 1 ? beta_nm(n, m) * qm[n - 1] : 0.0);
+        outQ[i] = m * qm[n];
+      }
+    }
+  }
+}
+
+static void upload(DevBuf& b, const void* src, size_t bytes) {
+  b.alloc(bytes);
+  BIE_HIP(hipMemcpy(b.ptr, src, bytes, hipMemcpyHostToDevice));
+}
+
+template <typename T>
+static void upload_vec(DevBuf& b, const std::vector<T>& v) {
+  upload(b, v.data(), v.size() * sizeof(T));
+}
+
+void build(bie_ctx* c, const double* centres, int64_t nb, const bie_opts* o) {
+  if (!centres || nb <= 0 || !o) throw Error{BIE_EINVAL, "null centres/opts or no spheres"};
+  if (o->p < 1 || o->p > 20) throw Error{BIE_EINVAL, "p must be in [1, 20]"};
+  int nphi = o->n_phi > 0 ? o->n_phi : 2 * o->p;
+  if (nphi < 2 * o->p || (nphi & 1)) throw Error{BIE_EINVAL, "n_phi must be even and >= 2p"};
+  if (nb > 65536) throw Error{BIE_EINVAL, "at most 65536 spheres per context"};
+  c->p = o->p;
+  c->n_phi = nphi;
+  c->mmax = std::min(o->p, nphi / 2 - 1);
+  c->nlat = o->p + 1;
+  c->P = c->nlat * nphi;
+  c->nb = nb;
+  c->N = nb * c->P;
+  c->near_gap = o->near_gap > 0 ? o->near_gap : 1.0;
+  c->device = o->device;
+  c->stream = (hipStream_t)o->hip_stream;
+  BIE_HIP(hipSetDevice(c->device));
+  c->centres.assign(centres, centres + 3 * nb);
+  for (double x : c->centres)
+    if (!std::isfinite(x)) throw Error{BIE_EINVAL, "non-finite centre coordinate"};
+
+  // ---- near pairs (Eq. 4.5 as a surface-gap test) with a uniform cell list --------
+  const double cut = 2.0 + c->near_gap;
+  const double cut2 = cut * cut;
+  double lo[3] = {1e300, 1e300, 1e300};
+  for (int64_t k = 0; k < nb; ++k)
+    for (int d = 0; d < 3; ++d) lo[d] = std::min(lo[d], centres[3 * k + d]);
+  std::unordered_map<int64_t, std::vector<int>> cells;
+  auto key = [](int64_t a, int64_t b, int64_t d) { return (a * 2097152 + b) * 2097152 + d; };
+  std::vector<int64_t> cidx(3 * nb);
+  for (int64_t k = 0; k < nb; ++k) {
+    for (int d = 0; d < 3; ++d) cidx[3 * k + d] = (int64_t)std::floor((centres[3 * k + d] - lo[d]) / cut);
+    cells[key(cidx[3 * k], cidx[3 * k + 1], cidx[3 * k + 2])].push_back((int)k);
+  }
+  std::vector<std::vector<int>> nbr(nb);
+  for (int64_t k = 0; k < nb; ++k) {
+    for (int dx = -1; dx <= 1; ++dx)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dz = -1; dz <= 1; ++dz) {
+          auto it = cells.find(key(cidx[3 * k] + dx, cidx[3 * k + 1] + dy, cidx[3 * k + 2] + dz));
+          if (it == cells.end()) continue;
+          for (int s : it->second) {
+            if (s == k) continue;
+            double ddx = centres[3 * k] - centres[3 * s];
+            double ddy = centres[3 * k + 1] - centres[3 * s + 1];
+            double ddz = centres[3 * k + 2] - centres[3 * s + 2];
+            double d2 = ((ddx * ddx) + (ddy * ddy)) + (ddz * ddz);
+            if (d2 < 4.0)
+              throw Error{BIE_EOVERLAP, "spheres " + std::to_string(k) + " and " + std::to_string(s) + " overlap"};
+            if (d2 < cut2) nbr[k].push_back(s);
+          }
+        }
+    std::sort(nbr[k].begin(), nbr[k].end());
+  }
+  c->near_ptr.assign(nb + 1, 0);
+  c->near_idx.clear();
+  for (int64_t k = 0; k < nb; ++k) {
+    c->near_idx.insert(c->near_idx.end(), nbr[k].begin(), nbr[k].end());
+    c->near_ptr[k + 1] = (int)c->near_idx.size();
+  }
+  c->nwords = (int)((nb + 31) / 32);
+  std::vector<uint32_t> ex((size_t)nb * c->nwords, 0u);
+  for (int64_t k = 0; k < nb; ++k) {
+    ex[(size_t)k * c->nwords + (k >> 5)] |= 1u << (k & 31);
+    for (int s : nbr[k]) ex[(size_t)k * c->nwords + (s >> 5)] |= 1u << (s & 31);
+  }
+
+  // ---- grid (Eq. 4.2) and weights (Eq. 4.4) ----------------------------------------
+  std::vector<double> tt, ww;
+  gauss_legendre(c->nlat, tt, ww);
+  c->t = tt;
+  c->lam = ww;
+  c->theta.resize(c->nlat);
+  c->wlat.resize(c->nlat);
+  for (int j = 0; j < c->nlat; ++j) {
+    c->theta[j] = std::acos(tt[j]);
+    c->wlat[j] = 2.0 * M_PI * ww[j] / nphi;
+  }
+  c->phi.resize(nphi);
+  for (int l = 0; l < nphi; ++l) c->phi[l] = 2.0 * M_PI * l / nphi;
+  const int P = c->P;
+  std::vector<double> otab(4 * P), frame(9 * P), wnode(P);
+  std::vector<float> otab_f(4 * P);
+  for (int j = 0; j < c->nlat; ++j) {
+    double tj = tt[j], sj = std::sqrt(std::max(0.0, 1.0 - tj * tj));
+    for (int l = 0; l < nphi; ++l) {
+      int g = j * nphi + l;
+      double cp = std::cos(c->phi[l]), sp = std::sin(c->phi[l]);
+      double x[3] = {sj * cp, sj * sp, tj};
+      for (int d = 0; d < 3; ++d) {
+        otab[4 * g + d] = x[d];
+        otab_f[4 * g + d] = (float)x[d];
+      }
+      otab[4 * g + 3] = 0.0;
+      otab_f[4 * g + 3] = 0.0f;
+      double fr[9] = {x[0], x[1], x[2], tj * cp, tj * sp, -sj, -sp, cp, 0.0};
+      for (int d = 0; d < 9; ++d) frame[9 * g + d] = fr[d];
+      wnode[g] = c->wlat[j];
+    }
+  }
+
+  // ---- transform tables -----------------------------------------------------------
+  c->coef_m.clear();
+  c->coef_n.clear();
+  c->coef_off.assign(c->mmax + 2, 0);
+  for (int m = 0; m <= c->mmax; ++m) {
+    c->coef_off[m] = (int)c->coef_m.size();
+    for (int n = m; n <= c->p; ++n) {
+      c->coef_m.push_back(m);
+      c->coef_n.push_back(n);
+    }
+  }
+  c->coef_off[c->mmax + 1] = (int)c->coef_m.size();
+  c->ncoef = (int)c->coef_m.size();
+  const int nc = c->ncoef, nl = c->nlat;
+  std::vector<double> leg(3 * (size_t)nc * nl);
+  std::vector<double> cp(nc), cd(nc), cq(nc);
+  for (int j = 0; j < nl; ++j) {
+    double sj = std::sqrt(std::max(0.0, 1.0 - tt[j] * tt[j]));
+    legendre_tables(c->p, c->mmax, tt[j], sj, c->coef_m, c->coef_n, cp.data(), cd.data(), cq.data());
+    for (int i = 0; i < nc; ++i) {
+      leg[(0 * (size_t)nc + i) * nl + j] = cp[i];
+      leg[(1 * (size_t)nc + i) * nl + j] = cd[i];
+      leg[(2 * (size_t)nc + i) * nl + j] = cq[i];
+    }
+  }
+  std::vector<double> dft((size_t)(c->mmax + 1) * nphi * 2);
+  for (int m = 0; m <= c->mmax; ++m)
+    for (int l = 0; l < nphi; ++l) {
+      double a = 2.0 * M_PI * (double)((m * l) % nphi) / nphi;
+      dft[((size_t)m * nphi + l) * 2 + 0] = std::cos(a);
+      dft[((size_t)m * nphi + l) * 2 + 1] = std::sin(a);
+    }
+  std::vector<int> modes(2 * nc);
+  for (int i = 0; i < nc; ++i) {
+    modes[2 * i] = c->coef_m[i];
+    modes[2 * i + 1] = c->coef_n[i];
+  }
+  // recurrence constants per coefficient slot (m, n) for the near-series kernel:
+  //   A_{n,m} = sqrt((4n^2-1)/(n^2-m^2)), B_{n,m} = sqrt(((n-1)^2-m^2)/(4(n-1)^2-1)).
+  //   m = 0:  [A_{n+1,0}, B_{n+1,0}, -sqrt(n(n+1)), 0, A_{n+2,1}, B_{n+2,1}]
+  //   m >= 1: [A_{n+2,m}, B_{n+2,m}, alpha_n^m, beta_n^m, sqrt(2m+3), sqrt((2m+1)/(2m))]
+  auto Anm = [](int n, int m) { return std::sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)m * m)); };
+  auto Bnm = [](int n, int m) {
+    return std::sqrt(((n - 1.0) * (n - 1.0) - (double)m * m) / (4.0 * (n - 1.0) * (n - 1.0) - 1.0));
+  };
+  std::vector<double> rec(6 * (size_t)nc, 0.0);
+  for (int i = 0; i < nc; ++i) {
+    const int m = c->coef_m[i], n = c->coef_n[i];
+    double* r = &rec[6 * (size_t)i];
+    if (m == 0) {
+      r[0] = Anm(n + 1, 0);
+      r[1] = Bnm(n + 1, 0);
+      r[2] = -std::sqrt((double)n * (n + 1.0));
+      r[3] = 0.0;
+      r[4] = Anm(n + 2, 1);
+      r[5] = Bnm(n + 2, 1);
+    } else {
+      r[0] = Anm(n + 2, m);
+      r[1] = Bnm(n + 2, m);
+      r[2] = alpha_nm(n, m);
+      r[3] = beta_nm(n, m);
+      r[4] = std::sqrt(2.0 * m + 3.0);
+      r[5] = std::sqrt((2.0 * m + 1.0) / (2.0 * m));
+    }
+  }
+  auto tof = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
+
+  // ---- device upload -------------------------------------------------------------
+  std::vector<double> c4(4 * nb);
+  for (int64_t k = 0; k < nb; ++k) {
+    for (int d = 0; d < 3; ++d) c4[4 * k + d] = centres[3 * k + d];
+    c4[4 * k + 3] = 0.0;
+  }
+  upload_vec(c->centres4, c4);
+  upload_vec(c->excl, ex);
+  upload_vec(c->dnear_ptr, c->near_ptr);
+  upload_vec(c->dnear_idx, c->near_idx.empty() ? std::vector<int>{0} : c->near_idx);
+  upload_vec(c->otab, otab);
+  upload_vec(c->otab_f, otab_f);
+  upload_vec(c->frame, frame);
+  upload_vec(c->wnode, wnode);
+  upload_vec(c->leg, leg);
+  upload_vec(c->leg_f, tof(leg));
+  upload_vec(c->dft, dft);
+  upload_vec(c->dft_f, tof(dft));
+  upload_vec(c->wlat_d, c->wlat);
+  upload_vec(c->wlat_f, tof(c->wlat));
+  upload_vec(c->modes, modes);
+  upload_vec(c->rec, rec);
+  c->coef.alloc((size_t)nb * 3 * nc * 2 * sizeof(double));
+  c->q.alloc((size_t)c->N * 4 * sizeof(double));
+  c->moments.alloc((size_t)nb * 6 * sizeof(double));
+  c->scal.alloc(262144 * sizeof(double));  // [0,1024) scalars, [1024,...) dot partials, [200000,...) Krylov host-exchange
+  // far-field source splits: enough work-groups to fill 256 CUs several times over
+  const int64_t tblocks = (c->N + 511) / 512;
+  int ns = (int)std::max<int64_t>(1, std::min<int64_t>((2048 + tblocks - 1) / tblocks, nb / 4));
+  c->nsplit = std::max(1, std::min(ns, 64));
+  c->partial.alloc((size_t)c->nsplit * c->N * 3 * sizeof(double));
+  BIE_HIP(hipDeviceSynchronize());
+}
+
+}  // namespace bie

@@ -1,0 +1,46 @@
+"""Host-only checks of the C ABI: the library loads and exports every entry point that
+include/bie.h declares; argument errors come back as error codes without a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bie.h")
+LIB = os.path.join(ROOT, "paper_1707_06551_amd", "libbie.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bie_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ["bie_build_spheres", "bie_apply_bio", "bie_solve_resistance", "bie_solve_mobility",
+                     "bie_free", "bie_last_error"]:
+        assert required in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libbie.so not built")
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(LIB)
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    from paper_1707_06551_amd import bie
+    assert sorted(bie.EXPORTED) == declared_functions()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libbie.so not built")
+def test_null_arguments_are_rejected_without_a_device():
+    L = ctypes.CDLL(LIB)
+    L.bie_apply_bio.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    L.bie_apply_bio.restype = ctypes.c_int
+    L.bie_last_error.restype = ctypes.c_char_p
+    assert L.bie_apply_bio(None, 3, 0, None, None) == -1
+    assert b"null" in L.bie_last_error()
+    L.bie_build_spheres.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
+    L.bie_build_spheres.restype = ctypes.c_int
+    assert L.bie_build_spheres(None, 0, None, None) == -1
