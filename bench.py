@@ -32,6 +32,22 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 
 
+def measured_traffic():
+    """HBM bytes per launch of the far-field kernel from the committed PMC summary, or
+    None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_1707_06551_amd", "csrc", "p2p.hip")
+    prof = os.path.join(ROOT, "profiles", "far_kernel_spheres512_p12_pmc.md")
+    try:
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        fields = dict(l.split(": ", 1) for l in open(prof).read().splitlines() if ": " in l and l[:1].isalpha())
+        if fields.get("source_sha256_16", "").strip() == sha:
+            return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        pass
+    return None
+
+
 def far_pairs(sph):
     """Pairs of nodes on distinct, well-separated spheres evaluated by one far-field pass."""
     near = sph.near_pairs().shape[1]
@@ -164,7 +180,8 @@ def main():
         "setup_s": t_setup,
         "roofline": {"bound": "alu", "kernel": f"far_kernel<float,{kind}> (float32 far-field pair sum)",
                      "achieved": ach32, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": ach32 / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+                     "frac": ach32 / PEAK_FP32_VECTOR_TFLOPS, "traffic": measured_traffic(),
+                     "traffic_unit": "bytes per launch (HBM, PMC FETCH_SIZE + WRITE_SIZE, calibrated)",
                      "flop_per_pair": FLOP_PER_PAIR[kind], "launch_ms": t_far32 * 1e3,
                      "pairs_per_launch": pairs_per_mv},
         "far_fp64": {"achieved_tflops": ach64, "peak": PEAK_FP64_VECTOR_TFLOPS, "frac": ach64 / PEAK_FP64_VECTOR_TFLOPS,

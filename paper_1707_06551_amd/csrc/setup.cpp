@@ -338,7 +338,8 @@ void build(bie_ctx* c, const double* centres, int64_t nb, const bie_opts* o) {
   c->scal.alloc(262144 * sizeof(double));  // [0,1024) scalars, [1024,...) dot partials, [200000,...) Krylov host-exchange
   // far-field source splits: enough work-groups to fill 256 CUs several times over
   const int64_t tblocks = (c->N + 511) / 512;
-  int ns = (int)std::max<int64_t>(1, std::min<int64_t>((2048 + tblocks - 1) / tblocks, nb / 4));
+  // (about 6144 work-groups: ~5 resident per CU, so the last partial round is short)
+  int ns = (int)std::max<int64_t>(1, std::min<int64_t>((6144 + tblocks - 1) / tblocks, nb / 2));
   c->nsplit = std::max(1, std::min(ns, 64));
   c->partial.alloc((size_t)c->nsplit * c->N * 3 * sizeof(double));
   BIE_HIP(hipDeviceSynchronize());

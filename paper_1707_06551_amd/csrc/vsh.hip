@@ -67,15 +67,17 @@ __global__ __launch_bounds__(256) void vsh_kernel(VshParams a) {
       fs[2 * P + g] = (R)(mx * fr[6] + my * fr[7] + mz * fr[8]);
       const double w = a.wnode[g];
       if (a.write_q) {
+        // far-field source: q = w mu and o . q (o = unit offset = e_r of the node)
+        const double oq = w * (mx * fr[0] + my * fr[1] + mz * fr[2]);
         if (a.q_float) {
-          float4 v = make_float4((float)(w * mx), (float)(w * my), (float)(w * mz), 0.0f);
+          float4 v = make_float4((float)(w * mx), (float)(w * my), (float)(w * mz), (float)oq);
           reinterpret_cast<float4*>(a.q)[base + g] = v;
         } else {
           double* qd = reinterpret_cast<double*>(a.q) + 4 * (base + g);
           qd[0] = w * mx;
           qd[1] = w * my;
           qd[2] = w * mz;
-          qd[3] = 0.0;
+          qd[3] = oq;
         }
       }
       if (a.want_moments) {
