@@ -200,3 +200,51 @@ def test_isolated_sphere_drag():
     vv, oo, _, info = s.solve_mobility(F, T, tol=1e-13)
     assert np.abs(vv - v).max() < 1e-12 and np.abs(oo - om).max() < 1e-12
     s.close()
+
+
+LARGE = ["spheres4096_p8", "spheres1024_p16", "spheres2048_p12_slip"]
+
+
+@pytest.mark.parametrize("wname", LARGE)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_sampled_parity_other_workloads(wname, precision):
+    # the remaining workload sizes (589,824 / 557,056 / 638,976 nodes) in the launch
+    # configuration a solve uses; oracle values for sampled targets (all nodes of the
+    # sphere with the most near neighbours, plus random nodes)
+    w = make_workload(wname)
+    B = _bie()
+    s = B.Spheres(w["centres"], w["p"], near_gap=1.0)
+    g = Geometry(w["centres"], w["p"], near_gap=1.0)
+    ops = Operators(g)
+    rng = np.random.default_rng(43)
+    opname = "DN_BIE" if w["problem"] == "resistance" else "SD_BIE"
+    mu = rng.standard_normal((g.N, 3))
+    out = host(s.apply(OPS[opname], dev(mu), precision=precision)).reshape(g.N, 3)
+    busiest = int(np.argmax(g.near.sum(axis=1)))
+    tg = np.concatenate([np.arange(busiest * g.P, (busiest + 1) * g.P), rng.choice(g.N, 64, replace=False)])
+    ref = ops.apply(opname, mu, targets=tg)
+    tol = 1e-11 if precision == 0 else 1e-6
+    assert rel_err(out[tg], ref) < tol, (rel_err(out[tg], ref), max_rel(out[tg], ref))
+    s.close()
+
+
+def test_slip_mobility_solve_is_consistent():
+    # active-slip mobility (Problem 4): the solved density reproduces the boundary
+    # condition u_s + v_i + omega_i x (x - c_i) when the bordered operator is reapplied
+    from paper_1707_06551_amd.inputs import slip_field
+    w = make_workload("spheres2048_p12_slip")
+    c = w["centres"][:48]
+    B = _bie()
+    s = B.Spheres(c, 8, near_gap=1.0)
+    xyz, _ = s.nodes()
+    k = np.repeat(np.arange(48), s.P)
+    normals = xyz - c[k]
+    us = slip_field(w["slip_coef"][:48], normals, k)
+    F = np.zeros((48, 3))
+    v, om, mu, info = s.solve_mobility(F, F, slip=dev(us), tol=1e-10, precision=1, precond=1, want_mu=True)
+    assert info["converged"], info
+    x = torch.cat([mu, dev(v), dev(om)])
+    out = host(s.apply(5, x, precision=0))
+    assert rel_err(out[:3 * s.N], us.reshape(-1)) < 1e-9
+    assert np.abs(out[3 * s.N:]).max() < 1e-9 * np.abs(us).max()
+    s.close()
