@@ -155,6 +155,78 @@ int bie_solve_resistance(bie_ctx* ctx, const double* v, const double* omega, con
 int bie_solve_mobility(bie_ctx* ctx, const double* F, const double* T, const double* slip,
                        const bie_solve_opts* opts, double* v, double* omega, double* mu, bie_solve_info* info);
 
+/* Generic solve of op (BIE_OP_DN_BIE or BIE_OP_MOBILITY) with a caller right-hand side:
+ * b, x device float64 of length 3N (3N + 6 n_b for mobility).  Same solver and return
+ * codes as bie_solve_resistance.  Synchronises the stream. */
+int bie_solve(bie_ctx* ctx, int op, const double* b, double* x, const bie_solve_opts* opts, bie_solve_info* info);
+
+/* z = M r for the preconditioner precond (BIE_PC_*) of op, in the given precision.
+ * r, z: device float64, length 3N (3N + 6 n_b for mobility), must not alias. */
+int bie_apply_precond(bie_ctx* ctx, int op, int precision, int precond, const double* r, double* z);
+
+/* ---- learned close-pair coarse correction (no counterpart in the paper) -------------
+ * Coarse space per sphere: the vector spherical harmonics of degree <= 2 (Definition
+ * 2.2) in a Cartesian parametrisation of 25 coefficients (s; a; b; c; tV; tW; tX):
+ *   s x,  a - 3 (a.x) x,  b,  c x x,  2 T x - 5 (x.T x) x,  2 T x,  2 x x (T x),
+ * x the unit normal, T = sum_k t_k E_k over the Frobenius-orthonormal symmetric
+ * traceless basis (xy, yz, xz, xx - yy, 2zz - xx - yy).  BIE_PC_MLP applies
+ *   z = M0 r + P zeta,  zeta_i = sum_{j near i} rot_ij^T [K_off rot_ij rho_j + K_self rot_ij rho_i],
+ * rho = R r (weighted projection with the Eq. 4.4 weights), P = synthesis, rot_ij the
+ * rotation into the frame whose z axis points from c_i to c_j, and K(theta) 25 x 25
+ * maps commuting with rotations about that axis (139 parameters each) produced per
+ * directed near pair by an MLP (8 -> 64 -> 64 -> 278, tanh, float32) of the pair's
+ * features: gap g, log(g + 0.01), 0.1/(g + 0.1), near counts of i and j / 8, smallest
+ * other gap of i and of j (near_gap if none), sum_{k near i} 0.1/(g_ik + 0.1).
+ * The correction acts on the resistance form; for mobility BIE_PC_MLP is M0. */
+
+/* rho = R f: f device 3N float64 -> rho device n_b x 25 float64. */
+int bie_lowmodes(bie_ctx* ctx, const double* f, double* rho);
+/* f = P rho (overwrites f). */
+int bie_lowmodes_synth(bie_ctx* ctx, const double* rho, double* f);
+
+/* Directed near pairs in CSR order (grouped by target sphere i), with features and
+ * frames.  Host outputs, each optional: pair_i, pair_j (count), feats (count x 8),
+ * frames (count x 34: Q row-major then D2 row-major, D2_kl = tr(E_k Q E_l Q^T)). */
+int bie_pair_geometry(const bie_ctx* ctx, int64_t* count, int32_t* pair_i, int32_t* pair_j, float* feats,
+                      double* frames);
+
+/* Number of MLP weights (flattened W1 8x64, b1, W2 64x64, b2, W3 64x278, b3). */
+int64_t bie_mlp_n_weights(void);
+
+/* Loads MLP weights (host, float32) into the context and evaluates theta for every
+ * directed near pair on the device; enables BIE_PC_MLP.  Rejects non-finite weights. */
+int bie_precond_load(bie_ctx* ctx, const float* weights, int64_t n_weights);
+
+/* Training set for the MLP: n_configs configurations concatenated; spheres and pairs
+ * are numbered globally, pairs grouped by target sphere (sph_ptr CSR) and by
+ * configuration (cfg_sph, cfg_pair offsets, n_configs + 1 each).  For each sphere and
+ * each of n_rhs samples: xi (n_spheres x n_rhs x 25) = R b of a right-hand side b = P xi,
+ * target (same layout) = R x - R M0 b for the solution of A x = b.  All host arrays. */
+typedef struct {
+  int64_t n_pairs, n_spheres, n_configs;
+  int32_t n_rhs;
+  const float* feats;      /* n_pairs x 8 */
+  const float* frames;     /* n_pairs x 34 */
+  const int32_t* pair_i;   /* n_pairs */
+  const int32_t* pair_j;   /* n_pairs */
+  const int32_t* sph_ptr;  /* n_spheres + 1 */
+  const int32_t* cfg_sph;  /* n_configs + 1 */
+  const int32_t* cfg_pair; /* n_configs + 1 */
+  const float* xi;
+  const float* target;
+} bie_mlp_data;
+
+/* Loss L = sum |target - zeta(xi)|^2 / sum |target|^2 and its gradient with respect to
+ * the weights (host float32, length bie_mlp_n_weights()) on the device of the calling
+ * thread, one forward and one backward pass over the whole set. */
+int bie_mlp_eval(const bie_mlp_data* data, const float* weights, double* loss, float* grad);
+
+/* Adam training (beta 0.9 / 0.999) for `epochs` passes over the set in batches of
+ * cfg_per_batch configurations; weights in: initial, out: trained; loss_hist (epochs,
+ * optional) receives the summed batch losses per epoch. */
+int bie_mlp_train(const bie_mlp_data* data, float* weights, int epochs, int cfg_per_batch, double lr,
+                  double* loss_hist);
+
 /* Thread-local message of the last error on this thread ("" if none). */
 const char* bie_last_error(void);
 

@@ -22,7 +22,20 @@ OK, ENOCONV, EINVAL, EOVERLAP, EDEVICE, ENOMEM = 0, 1, -1, -2, -3, -4
 EXPORTED = [
     "bie_build_spheres", "bie_free", "bie_sizes", "bie_get_nodes", "bie_near_pairs", "bie_apply_bio",
     "bie_vsh_forward", "bie_vsh_inverse", "bie_solve_resistance", "bie_solve_mobility", "bie_last_error",
+    "bie_solve", "bie_apply_precond", "bie_lowmodes", "bie_lowmodes_synth", "bie_pair_geometry",
+    "bie_mlp_n_weights", "bie_precond_load", "bie_mlp_eval", "bie_mlp_train",
 ]
+NLOW = 25
+NFEAT = 8
+NFRAME = 34
+
+
+class MlpData(ctypes.Structure):
+    _fields_ = [("n_pairs", ctypes.c_int64), ("n_spheres", ctypes.c_int64), ("n_configs", ctypes.c_int64),
+                ("n_rhs", ctypes.c_int32), ("feats", ctypes.c_void_p), ("frames", ctypes.c_void_p),
+                ("pair_i", ctypes.c_void_p), ("pair_j", ctypes.c_void_p), ("sph_ptr", ctypes.c_void_p),
+                ("cfg_sph", ctypes.c_void_p), ("cfg_pair", ctypes.c_void_p), ("xi", ctypes.c_void_p),
+                ("target", ctypes.c_void_p)]
 
 
 class Opts(ctypes.Structure):
@@ -78,8 +91,86 @@ def lib():
     L.bie_solve_mobility.restype = I
     L.bie_last_error.argtypes = []
     L.bie_last_error.restype = ctypes.c_char_p
+    L.bie_solve.argtypes = [VP, I, VP, VP, P(SolveOpts), P(SolveInfo)]
+    L.bie_solve.restype = I
+    L.bie_apply_precond.argtypes = [VP, I, I, I, VP, VP]
+    L.bie_apply_precond.restype = I
+    L.bie_lowmodes.argtypes = [VP, VP, VP]
+    L.bie_lowmodes.restype = I
+    L.bie_lowmodes_synth.argtypes = [VP, VP, VP]
+    L.bie_lowmodes_synth.restype = I
+    L.bie_pair_geometry.argtypes = [VP, P(I64), VP, VP, VP, VP]
+    L.bie_pair_geometry.restype = I
+    L.bie_mlp_n_weights.argtypes = []
+    L.bie_mlp_n_weights.restype = I64
+    L.bie_precond_load.argtypes = [VP, VP, I64]
+    L.bie_precond_load.restype = I
+    L.bie_mlp_eval.argtypes = [P(MlpData), VP, P(D), VP]
+    L.bie_mlp_eval.restype = I
+    L.bie_mlp_train.argtypes = [P(MlpData), VP, I, I, D, VP]
+    L.bie_mlp_train.restype = I
     _lib = L
     return L
+
+
+def mlp_n_weights():
+    return int(lib().bie_mlp_n_weights())
+
+
+class TrainingSet:
+    """Host-side packing of MLP training data (see bie_mlp_data in include/bie.h)."""
+
+    def __init__(self, n_rhs):
+        self.n_rhs = n_rhs
+        self.feats, self.frames, self.pi, self.pj, self.xi, self.t = [], [], [], [], [], []
+        self.cfg_sph, self.cfg_pair = [0], [0]
+        self.sph_ptr = [0]
+
+    def add(self, pair_i, pair_j, feats, frames, xi, target):
+        """One configuration: pairs grouped by target sphere; xi, target (nb, n_rhs, 25)."""
+        s0, p0 = self.cfg_sph[-1], self.cfg_pair[-1]
+        nb = xi.shape[0]
+        counts = np.bincount(pair_i, minlength=nb)
+        self.pi.append(pair_i.astype(np.int32) + s0)
+        self.pj.append(pair_j.astype(np.int32) + s0)
+        self.feats.append(np.asarray(feats, np.float32))
+        self.frames.append(np.asarray(frames, np.float32))
+        self.xi.append(np.asarray(xi, np.float32))
+        self.t.append(np.asarray(target, np.float32))
+        self.sph_ptr.extend((p0 + np.cumsum(counts)).tolist())
+        self.cfg_sph.append(s0 + nb)
+        self.cfg_pair.append(p0 + len(pair_i))
+
+    def pack(self):
+        cat = lambda xs, dt, w: np.ascontiguousarray(np.concatenate(xs).astype(dt)) if xs else np.zeros((0, w), dt)
+        self._arrs = dict(
+            feats=cat(self.feats, np.float32, NFEAT), frames=cat(self.frames, np.float32, NFRAME),
+            pi=cat(self.pi, np.int32, 1), pj=cat(self.pj, np.int32, 1),
+            sph=np.ascontiguousarray(np.array(self.sph_ptr, np.int32)),
+            cs=np.ascontiguousarray(np.array(self.cfg_sph, np.int32)),
+            cp=np.ascontiguousarray(np.array(self.cfg_pair, np.int32)),
+            xi=cat(self.xi, np.float32, 1), t=cat(self.t, np.float32, 1))
+        a = self._arrs
+        d = MlpData(a["pi"].size, a["cs"][-1], len(self.cfg_sph) - 1, self.n_rhs, _hptr(a["feats"]),
+                    _hptr(a["frames"]), _hptr(a["pi"]), _hptr(a["pj"]), _hptr(a["sph"]), _hptr(a["cs"]),
+                    _hptr(a["cp"]), _hptr(a["xi"]), _hptr(a["t"]))
+        self._data = d
+        return d
+
+    def eval(self, weights):
+        d = self.pack()
+        w = np.ascontiguousarray(weights, np.float32)
+        g = np.empty_like(w)
+        loss = ctypes.c_double()
+        _check(lib().bie_mlp_eval(ctypes.byref(d), _hptr(w), ctypes.byref(loss), _hptr(g)))
+        return loss.value, g
+
+    def train(self, weights, epochs, cfg_per_batch=8, lr=1e-3):
+        d = self.pack()
+        w = np.ascontiguousarray(weights, np.float32).copy()
+        hist = np.zeros(max(1, epochs))
+        _check(lib().bie_mlp_train(ctypes.byref(d), _hptr(w), epochs, cfg_per_batch, lr, _hptr(hist)))
+        return w, hist[:epochs]
 
 
 class BieError(RuntimeError):
@@ -169,6 +260,49 @@ class Spheres:
         u = torch.empty(3 * self.N, dtype=torch.float64, device=coef.device)
         _check(lib().bie_vsh_inverse(self._h, precision, _dptr(coef), _dptr(u)))
         return u
+
+    def solve(self, op, b, tol=1e-8, restart=100, max_iter=1000, precision=FP64, precond=PC_NONE, inner_tol=1e-4):
+        """Generic solve A x = b (device tensors) for OP_DN_BIE or OP_MOBILITY."""
+        import torch
+        x = torch.empty_like(b)
+        info = SolveInfo()
+        so = self._sopts(tol, restart, max_iter, precision, precond, inner_tol)
+        rc = lib().bie_solve(self._h, op, _dptr(b), _dptr(x), ctypes.byref(so), ctypes.byref(info))
+        _check(rc, allow_noconv=True)
+        return x, dict(info.as_dict(), converged=(rc == OK))
+
+    def apply_precond(self, op, r, precond=PC_M0, precision=FP64):
+        import torch
+        z = torch.empty_like(r)
+        _check(lib().bie_apply_precond(self._h, op, precision, precond, _dptr(r), _dptr(z)))
+        return z
+
+    def lowmodes(self, f):
+        import torch
+        rho = torch.empty(self.nb * NLOW, dtype=torch.float64, device=f.device)
+        _check(lib().bie_lowmodes(self._h, _dptr(f), _dptr(rho)))
+        return rho
+
+    def lowmodes_synth(self, rho):
+        import torch
+        f = torch.empty(3 * self.N, dtype=torch.float64, device=rho.device)
+        _check(lib().bie_lowmodes_synth(self._h, _dptr(rho), _dptr(f)))
+        return f
+
+    def pair_geometry(self):
+        cnt = ctypes.c_int64()
+        _check(lib().bie_pair_geometry(self._h, ctypes.byref(cnt), None, None, None, None))
+        n = cnt.value
+        pi = np.empty(n, np.int32)
+        pj = np.empty(n, np.int32)
+        feats = np.empty((n, NFEAT), np.float32)
+        frames = np.empty((n, NFRAME), np.float64)
+        _check(lib().bie_pair_geometry(self._h, ctypes.byref(cnt), _hptr(pi), _hptr(pj), _hptr(feats), _hptr(frames)))
+        return pi, pj, feats, frames
+
+    def load_precond(self, weights):
+        w = np.ascontiguousarray(weights, np.float32)
+        _check(lib().bie_precond_load(self._h, _hptr(w), w.size))
 
     @staticmethod
     def _sopts(tol, restart, max_iter, precision, precond, inner_tol):

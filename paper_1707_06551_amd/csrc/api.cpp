@@ -98,6 +98,28 @@ void dev_precond_m0(bie_ctx* c, int op_base, int precision, const double* r, dou
   launch_vsh(c, precision, v);
 }
 
+void apply_precond(bie_ctx* c, int op_base, int precision, int precond, const double* r, double* z) {
+  if (op_base != BIE_OP_DN_BIE && op_base != BIE_OP_MOBILITY)
+    throw Error{BIE_EINVAL, "preconditioners exist for BIE_OP_DN_BIE and BIE_OP_MOBILITY"};
+  if (precision != BIE_FP64 && precision != BIE_MIXED) throw Error{BIE_EINVAL, "bad precision"};
+  const int64_t n = 3 * c->N + (op_base == BIE_OP_MOBILITY ? 6 * c->nb : 0);
+  switch (precond) {
+    case BIE_PC_NONE:
+      dev_copy(c, r, z, n);
+      return;
+    case BIE_PC_M0:
+      dev_precond_m0(c, op_base, precision, r, z);
+      return;
+    case BIE_PC_MLP:
+      if (!c->theta_ready) throw Error{BIE_EINVAL, "BIE_PC_MLP needs bie_precond_load first"};
+      dev_precond_m0(c, op_base, precision, r, z);
+      if (op_base == BIE_OP_DN_BIE) coarse_correct(c, r, z);
+      return;
+    default:
+      throw Error{BIE_EINVAL, "unknown preconditioner"};
+  }
+}
+
 }  // namespace bie
 
 using bie::Error;
@@ -310,6 +332,81 @@ int bie_solve_mobility(bie_ctx* c, const double* F, const double* T, const doubl
     x.release();
   });
   return rc;
+}
+
+int bie_solve(bie_ctx* c, int op, const double* b, double* x, const bie_solve_opts* opts, bie_solve_info* info) {
+  if (!c || !b || !x) {
+    bie::set_error("null argument");
+    return BIE_EINVAL;
+  }
+  if (op != BIE_OP_DN_BIE && op != BIE_OP_MOBILITY) {
+    bie::set_error("bie_solve supports BIE_OP_DN_BIE and BIE_OP_MOBILITY");
+    return BIE_EINVAL;
+  }
+  int rc = BIE_OK;
+  const int64_t n = 3 * c->N + (op == BIE_OP_MOBILITY ? 6 * c->nb : 0);
+  BIE_TRY(rc = bie::solve(c, op, b, x, n, opts, info));
+  return rc;
+}
+
+int bie_apply_precond(bie_ctx* c, int op, int precision, int precond, const double* r, double* z) {
+  if (!c || !r || !z || r == z) {
+    bie::set_error("null or aliased argument");
+    return BIE_EINVAL;
+  }
+  BIE_TRY(bie::apply_precond(c, op, precision, precond, r, z));
+  return BIE_OK;
+}
+
+int bie_lowmodes(bie_ctx* c, const double* f, double* rho) {
+  if (!c || !f || !rho) return BIE_EINVAL;
+  BIE_TRY(bie::lowmode_restrict(c, f, rho));
+  return BIE_OK;
+}
+
+int bie_lowmodes_synth(bie_ctx* c, const double* rho, double* f) {
+  if (!c || !f || !rho) return BIE_EINVAL;
+  BIE_TRY(bie::lowmode_prolong(c, rho, f, false));
+  return BIE_OK;
+}
+
+int bie_pair_geometry(const bie_ctx* c, int64_t* count, int32_t* pair_i, int32_t* pair_j, float* feats,
+                      double* frames) {
+  if (!c || !count) return BIE_EINVAL;
+  const int64_t np = (int64_t)c->near_idx.size();
+  *count = np;
+  for (int64_t i = 0; i < c->nb; ++i)
+    for (int e = c->near_ptr[i]; e < c->near_ptr[i + 1]; ++e) {
+      if (pair_i) pair_i[e] = (int32_t)i;
+      if (pair_j) pair_j[e] = c->near_idx[e];
+    }
+  if (feats && np) std::memcpy(feats, c->pair_feat.data(), c->pair_feat.size() * sizeof(float));
+  if (frames && np) std::memcpy(frames, c->pair_frame.data(), c->pair_frame.size() * sizeof(double));
+  return BIE_OK;
+}
+
+int64_t bie_mlp_n_weights(void) { return bie::mlp_n_weights(); }
+
+int bie_precond_load(bie_ctx* c, const float* weights, int64_t n_weights) {
+  if (!c || !weights || n_weights != bie::mlp_n_weights()) {
+    bie::set_error("null context / weights or wrong weight count");
+    return BIE_EINVAL;
+  }
+  BIE_TRY(bie::mlp_infer(c, weights));
+  return BIE_OK;
+}
+
+int bie_mlp_eval(const bie_mlp_data* data, const float* weights, double* loss, float* grad) {
+  if (!data || !weights || !loss || !grad) return BIE_EINVAL;
+  BIE_TRY(*loss = bie::mlp_eval(data, weights, grad));
+  return BIE_OK;
+}
+
+int bie_mlp_train(const bie_mlp_data* data, float* weights, int epochs, int cfg_per_batch, double lr,
+                  double* loss_hist) {
+  if (!data || !weights) return BIE_EINVAL;
+  BIE_TRY(bie::mlp_train(data, weights, epochs, cfg_per_batch, lr, loss_hist));
+  return BIE_OK;
 }
 
 const char* bie_last_error(void) { return bie::last_error(); }

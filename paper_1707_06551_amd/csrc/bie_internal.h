@@ -90,6 +90,16 @@ struct bie_ctx {
   bie::DevBuf krylov, zbasis, vec[6];
   int krylov_cols = 0;
   int64_t krylov_n = 0;
+
+  // learned coarse correction (coarse.hip, mlp.hip)
+  bie::DevBuf lowF;                 // P x 25 x 3 double: low-mode basis fields at the nodes
+  bie::DevBuf lownorm;              // 25 double: their squared norms
+  std::vector<float> pair_feat;     // directed near pairs (CSR order) x 8 features
+  std::vector<double> pair_frame;   // directed near pairs x 34: Q and D2
+  bie::DevBuf dframe;               // device copy of pair_frame
+  bie::DevBuf mlp_theta;            // near pairs x 278 float: MLP output
+  bie::DevBuf rho, zeta;            // nb x 25 double
+  bool theta_ready = false;
 };
 
 namespace bie {
@@ -122,4 +132,15 @@ void dev_fill(bie_ctx* c, double* y, double v, int64_t n);
 double dev_norm(bie_ctx* c, const double* x, int64_t n);
 void dev_rigid_rhs(bie_ctx* c, const double* v_dev, const double* om_dev, double* b);
 void dev_precond_m0(bie_ctx* c, int op_base, int precision, const double* r, double* z);
+void apply_precond(bie_ctx* c, int op_base, int precision, int precond, const double* r, double* z);
+
+// learned coarse correction
+void build_coarse(bie_ctx* c);
+void lowmode_restrict(bie_ctx* c, const double* f, double* rho);
+void lowmode_prolong(bie_ctx* c, const double* rho, double* f, bool accumulate);
+void coarse_correct(bie_ctx* c, const double* r, double* z);
+int64_t mlp_n_weights();
+double mlp_eval(const bie_mlp_data* d, const float* weights, float* grad);
+void mlp_train(const bie_mlp_data* d, float* weights, int epochs, int cfg_per_batch, double lr, double* loss_hist);
+void mlp_infer(bie_ctx* c, const float* weights);
 }  // namespace bie

@@ -342,6 +342,7 @@ void build(bie_ctx* c, const double* centres, int64_t nb, const bie_opts* o) {
   int ns = (int)std::max<int64_t>(1, std::min<int64_t>((6144 + tblocks - 1) / tblocks, nb / 2));
   c->nsplit = std::max(1, std::min(ns, 64));
   c->partial.alloc((size_t)c->nsplit * c->N * 3 * sizeof(double));
+  build_coarse(c);
   BIE_HIP(hipDeviceSynchronize());
 }
 

@@ -154,11 +154,8 @@ void apply_A(const OpCtx& o, const double* x, double* y) {
 }
 
 void apply_M(const OpCtx& o, const double* x, double* z, int64_t n) {
-  if (o.precond == BIE_PC_NONE) {
-    dev_copy(o.c, x, z, n);
-    return;
-  }
-  dev_precond_m0(o.c, o.op, o.precision, x, z);
+  (void)n;
+  apply_precond(o.c, o.op, o.precision, o.precond, x, z);
 }
 
 // One flexible GMRES solve of A d = r from d = 0 to relative tolerance tol (estimate);
@@ -174,7 +171,7 @@ int fgmres(const OpCtx& o, Krylov& K, const double* r, double rnorm, double tol,
   int it = 0;
   double cur = rnorm;
   const double* rr = r;
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hh(2 * (m + 1) + 1);
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hh(2 * (m + 1) + 1), ests;
   while (it < max_it) {
     // V_0 = current residual / its norm.  First cycle: r; later cycles: r - A d.
     if (rr == r) {
@@ -228,6 +225,15 @@ int fgmres(const OpCtx& o, Krylov& K, const double* r, double rnorm, double tol,
         *bad = true;
         return it;
       }
+      // stagnation of a preconditioned solve: less than 10% reduction in 20 steps
+      if (K.flexible) {
+        ests.push_back(est);
+        const size_t q = ests.size();
+        if (q > 20 && ests[q - 1] > 0.9 * ests[q - 21]) {
+          *bad = true;
+          return it;
+        }
+      }
       if (hist) hist->push_back(est / rnorm);
       if (est <= tol * rnorm || den == 0.0) {
         ++j;
@@ -266,7 +272,8 @@ int solve(bie_ctx* c, int op, const double* b, double* x, int64_t n, const bie_s
   if (o.max_iter <= 0) o.max_iter = 1000;
   if (!(o.inner_tol > 0)) o.inner_tol = 1e-4;
   if (o.restart > 500) throw Error{BIE_EINVAL, "restart must be <= 500"};
-  if (o.precond == BIE_PC_MLP) throw Error{BIE_EINVAL, "learned preconditioner is not available"};
+  if (o.precond == BIE_PC_MLP && !c->theta_ready) throw Error{BIE_EINVAL, "BIE_PC_MLP needs bie_precond_load first"};
+  if (o.precond < BIE_PC_NONE || o.precond > BIE_PC_MLP) throw Error{BIE_EINVAL, "unknown preconditioner"};
   const int m = o.restart;
   const bool flexible = o.precond != BIE_PC_NONE;
   // work space

@@ -1,0 +1,117 @@
+"""Training driver of the learned close-pair coarse correction (BIE_PC_MLP).
+
+Data: for each training configuration (seeded placements of the 64-sphere training
+workload), random low-mode right-hand sides b = P xi (xi ~ N(0, 1), 25 coefficients per
+sphere) are solved with the plain float64 method (A x = b, completed double-layer
+form); the target is t = R x - R M0 b, the part of the low-mode response that the
+isolated-sphere inverse M0 misses.  Training runs on the GPU in the library's own
+forward / backward / Adam kernels (bie_mlp_train).
+
+Usage: python -m paper_1707_06551_amd.precond_train --configs 200 --rhs 4 --p 16 --epochs 300
+"""
+import argparse
+import json
+import os
+import time
+
+import numpy as np
+
+from . import bie
+from .inputs import make_workload
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_WEIGHTS = os.path.join(HERE, "weights", "precond_dn.npz")
+HIDDEN = 64
+
+
+def init_weights(seed=0, out_scale=1e-3):
+    """Glorot-uniform hidden layers, a small output layer (the correction starts near 0)."""
+    rng = np.random.default_rng(seed)
+    shapes = [(bie.NFEAT, HIDDEN), (HIDDEN,), (HIDDEN, HIDDEN), (HIDDEN,), (HIDDEN, 278), (278,)]
+    parts = []
+    for s in shapes:
+        if len(s) == 1:
+            parts.append(np.zeros(s))
+        else:
+            lim = np.sqrt(6.0 / (s[0] + s[1])) * (out_scale if s[1] == 278 else 1.0)
+            parts.append(rng.uniform(-lim, lim, s))
+    w = np.concatenate([p.reshape(-1) for p in parts]).astype(np.float32)
+    assert w.size == bie.mlp_n_weights()
+    return w
+
+
+def config_samples(sph, n_rhs, rng, tol=1e-8):
+    """(xi, target) of one configuration: (nb, n_rhs, 25) each, plus solve statistics."""
+    import torch
+    xi = rng.standard_normal((sph.nb, n_rhs, bie.NLOW))
+    target = np.empty_like(xi)
+    iters = []
+    for r in range(n_rhs):
+        rho = torch.from_numpy(np.ascontiguousarray(xi[:, r, :]).reshape(-1)).cuda()
+        b = sph.lowmodes_synth(rho)
+        x, info = sph.solve(bie.OP_DN_BIE, b, tol=tol, precision=bie.FP64, precond=bie.PC_M0)
+        if not info["converged"]:
+            raise RuntimeError(f"training solve did not converge: {info}")
+        iters.append(info["iters"])
+        z0 = sph.apply_precond(bie.OP_DN_BIE, b, precond=bie.PC_M0)
+        t = sph.lowmodes(x) - sph.lowmodes(z0)
+        torch.cuda.synchronize()
+        target[:, r, :] = t.cpu().numpy().reshape(sph.nb, bie.NLOW)
+    return xi, target, iters
+
+
+def build_set(n_configs, n_rhs, p, seed0=1000, workload="spheres64_p16_train", log=print):
+    ts = bie.TrainingSet(n_rhs)
+    t0 = time.time()
+    for k in range(n_configs):
+        w = make_workload(workload, seed=seed0 + k)
+        sph = bie.Spheres(w["centres"], p, near_gap=1.0)
+        pi, pj, feats, frames = sph.pair_geometry()
+        xi, target, iters = config_samples(sph, n_rhs, np.random.default_rng(seed0 + k + 7919))
+        ts.add(pi, pj, feats, frames, xi, target)
+        sph.close()
+        if log and (k % 20 == 0 or k == n_configs - 1):
+            log(f"config {k + 1}/{n_configs}: {len(pi)} pairs, solve iters {iters}, {time.time() - t0:.1f} s")
+    return ts
+
+
+def save_weights(path, w, meta):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    np.savez(path, weights=np.asarray(w, np.float32), meta=np.array(json.dumps(meta)))
+
+
+def load_weights(path=DEFAULT_WEIGHTS):
+    with np.load(path, allow_pickle=False) as z:
+        return z["weights"].astype(np.float32), json.loads(str(z["meta"]))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--configs", type=int, default=200)
+    ap.add_argument("--holdout", type=int, default=20)
+    ap.add_argument("--rhs", type=int, default=4)
+    ap.add_argument("--p", type=int, default=16)
+    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    args = ap.parse_args()
+    train = build_set(args.configs, args.rhs, args.p, seed0=1000)
+    hold = build_set(args.holdout, args.rhs, args.p, seed0=900000)
+    w0 = init_weights(0)
+    l0, _ = hold.eval(w0)
+    t0 = time.time()
+    w, hist = train.train(w0, args.epochs, cfg_per_batch=args.batch, lr=args.lr)
+    t_train = time.time() - t0
+    l1, _ = hold.eval(w)
+    ltr, _ = train.eval(w)
+    meta = dict(version=1, formulation="DN_BIE", p=args.p, hidden=HIDDEN, nfeat=bie.NFEAT, nout=278,
+                configs=args.configs, rhs=args.rhs, epochs=args.epochs, lr=args.lr, batch=args.batch,
+                train_loss=float(ltr), holdout_loss_init=float(l0), holdout_loss=float(l1),
+                train_seconds=t_train)
+    save_weights(args.out, w, meta)
+    print(json.dumps(dict(meta, loss_hist_first=float(hist[0]), loss_hist_last=float(hist[-1]))))
+
+
+if __name__ == "__main__":
+    main()

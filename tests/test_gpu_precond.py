@@ -1,0 +1,152 @@
+"""GPU parity of the learned coarse correction against the oracle (oracle/coarse.py,
+oracle/mlp.py, oracle/precond.py): pair geometry, low-mode restriction/prolongation,
+MLP loss and gradients (float32 kernels vs float64 oracle, 1e-3), the preconditioner
+application, and the gain of the trained network over M0."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import coarse, mlp
+from oracle.grid import Geometry
+from oracle.precond import m0_resistance
+from tests.gpu_common import max_rel, rel_err, small_cluster
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _bie():
+    from paper_1707_06551_amd import bie
+    return bie
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).reshape(-1)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def oracle_frames(dirs):
+    out = np.zeros((len(dirs), 34))
+    for e, d in enumerate(dirs):
+        Q = coarse.pair_frame(d)
+        out[e, :9] = Q.reshape(-1)
+        out[e, 9:] = coarse.rot25(Q)[10:15, 10:15].reshape(-1)
+    return out
+
+
+@pytest.fixture(scope="module")
+def cluster():
+    c = small_cluster(10, 7.0, 0.05, 21)
+    p = 5
+    B = _bie()
+    s = B.Spheres(c, p, near_gap=1.0)
+    g = Geometry(c, p, near_gap=1.0)
+    yield c, p, s, g
+    s.close()
+
+
+def test_pair_geometry_matches_oracle(cluster):
+    c, p, s, g = cluster
+    pi, pj, feats, frames = s.pair_geometry()
+    pairs, f_o, dirs = coarse.pair_features(c, g.near, 1.0)
+    assert np.array_equal(np.stack([pi, pj], 1), pairs)
+    assert np.abs(feats - f_o).max() < 1e-5
+    assert np.abs(frames - oracle_frames(dirs)).max() < 1e-13
+
+
+def test_lowmodes_match_oracle(cluster):
+    c, p, s, g = cluster
+    rng = np.random.default_rng(3)
+    f = rng.standard_normal((g.N, 3))
+    rho = host(s.lowmodes(dev(f))).reshape(g.nb, 25)
+    xh = g.grid["xhat"]
+    w = g.grid["wnode"]
+    ref = np.stack([coarse.restrict(f[g.sphere_nodes(k)], xh, w) for k in range(g.nb)])
+    assert max_rel(rho, ref) < 1e-12
+    back = host(s.lowmodes_synth(dev(ref))).reshape(g.N, 3)
+    refb = np.concatenate([coarse.prolong(ref[k], xh) for k in range(g.nb)])
+    assert max_rel(back, refb) < 1e-12
+
+
+def _dataset(rng, B):
+    data, ts = [], B.TrainingSet(2)
+    for seed, n in ((31, 7), (32, 9)):
+        c = small_cluster(n, 6.8, 0.05, seed)
+        g = Geometry(c, 3, near_gap=1.0)
+        pairs, feats, dirs = coarse.pair_features(c, g.near, 1.0)
+        xi = rng.standard_normal((2, g.nb, 25))
+        t = rng.standard_normal((2, g.nb, 25))
+        data.append(dict(pairs=pairs, feats=feats, dirs=dirs, xi=xi, t=t))
+        ts.add(pairs[:, 0], pairs[:, 1], feats, oracle_frames(dirs), xi.transpose(1, 0, 2), t.transpose(1, 0, 2))
+    return data, ts
+
+
+def test_mlp_loss_and_gradient_match_oracle():
+    B = _bie()
+    rng = np.random.default_rng(5)
+    data, ts = _dataset(rng, B)
+    w = mlp.init_weights(11, out_scale=0.3)
+    L, g = mlp.loss_and_grad(w, data)
+    # the oracle sees the float32 inputs the kernels see
+    w32 = w.astype(np.float32)
+    Lg, gg = ts.eval(w32)
+    assert abs(Lg - L) / L < 1e-4, (Lg, L)
+    assert np.linalg.norm(gg - g) / np.linalg.norm(g) < 1e-3
+    big = np.abs(g) > 1e-3 * np.abs(g).max()
+    assert np.median(np.abs(gg[big] - g[big]) / np.abs(g[big])) < 1e-3
+
+
+def test_training_kernels_reduce_the_loss():
+    B = _bie()
+    rng = np.random.default_rng(6)
+    data, ts = _dataset(rng, B)
+    # a learnable target: the correction of a fixed random network
+    wt = mlp.init_weights(12, out_scale=0.5)
+    for d in data:
+        theta, _ = mlp.forward(wt, d["feats"])
+        d["t"] = mlp.predict(d["pairs"], d["dirs"], theta, d["xi"])
+    ts2 = B.TrainingSet(2)
+    for d in data:
+        ts2.add(d["pairs"][:, 0], d["pairs"][:, 1], d["feats"], oracle_frames(d["dirs"]), d["xi"].transpose(1, 0, 2),
+                d["t"].transpose(1, 0, 2))
+    w0 = mlp.init_weights(13).astype(np.float32)
+    l0, _ = ts2.eval(w0)
+    w1, hist = ts2.train(w0, 300, cfg_per_batch=1, lr=3e-3)
+    l1, _ = ts2.eval(w1)
+    assert l1 < 0.2 * l0, (l0, l1, hist[:3], hist[-3:])
+    # the oracle agrees on the trained loss
+    assert abs(mlp.loss_and_grad(w1.astype(np.float64), data)[0] - l1) < 1e-3 * max(l1, 1e-3)
+
+
+def test_precond_mlp_application_matches_oracle(cluster):
+    c, p, s, g = cluster
+    B = _bie()
+    w = mlp.init_weights(17, out_scale=0.2)
+    s.load_precond(w.astype(np.float32))
+    rng = np.random.default_rng(8)
+    r = rng.standard_normal((g.N, 3))
+    z = host(s.apply_precond(B.OP_DN_BIE, dev(r), precond=B.PC_MLP)).reshape(g.N, 3)
+    pairs, feats, dirs = coarse.pair_features(c, g.near, 1.0)
+    theta, _ = mlp.forward(w.astype(np.float32).astype(np.float64), feats.astype(np.float32).astype(np.float64))
+    xh, wq = g.grid["xhat"], g.grid["wnode"]
+    rho = np.stack([coarse.restrict(r[g.sphere_nodes(k)], xh, wq) for k in range(g.nb)])
+    zeta = coarse.coarse_apply(pairs, dirs, theta, rho)
+    ref = m0_resistance(g, r) + np.concatenate([coarse.prolong(zeta[k], xh) for k in range(g.nb)])
+    assert rel_err(z, ref) < 1e-5, rel_err(z, ref)
+    # the M0 part alone is exact to rounding
+    z0 = host(s.apply_precond(B.OP_DN_BIE, dev(r), precond=B.PC_M0)).reshape(g.N, 3)
+    assert rel_err(z0, m0_resistance(g, r)) < 1e-12
+
+
+def test_nonfinite_weights_are_rejected(cluster):
+    c, p, s, g = cluster
+    B = _bie()
+    w = np.zeros(B.mlp_n_weights(), np.float32)
+    w[5] = np.nan
+    with pytest.raises(B.BieError):
+        s.load_precond(w)
