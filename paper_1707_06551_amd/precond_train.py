@@ -5,7 +5,10 @@ workload), random low-mode right-hand sides b = P xi (xi ~ N(0, 1), 25 coefficie
 sphere) are solved with the plain float64 method (A x = b, completed double-layer
 form); the target is t = R x - R M0 b, the part of the low-mode response that the
 isolated-sphere inverse M0 misses.  Training runs on the GPU in the library's own
-forward / backward / Adam kernels (bie_mlp_train).
+forward / backward / Adam kernels (bie_mlp_train).  Applied at full strength the
+additive correction over-corrects, so a relaxation omega (theta -> omega theta) is
+chosen on held-out configurations by GMRES iteration count and folded into the saved
+output layer.
 
 Usage: python -m paper_1707_06551_amd.precond_train --configs 200 --rhs 4 --p 16 --epochs 300
 """
@@ -75,6 +78,38 @@ def build_set(n_configs, n_rhs, p, seed0=1000, workload="spheres64_p16_train", l
     return ts
 
 
+OFF_W3 = bie.NFEAT * HIDDEN + HIDDEN + HIDDEN * HIDDEN + HIDDEN   # output layer (W3, b3) start
+
+
+def scaled(w, omega):
+    """Weights whose output (theta) is omega times that of w (theta is linear in W3, b3)."""
+    ws = np.array(w, dtype=np.float32, copy=True)
+    ws[OFF_W3:] *= omega
+    return ws
+
+
+def select_relaxation(w, p, seeds, omegas=(0.1, 0.15, 0.2, 0.25, 0.3, 0.4, 0.6, 1.0), workload="spheres64_p16_train",
+                      log=print):
+    """The additive correction over-corrects at full strength; choose the relaxation
+    omega (theta -> omega theta) that minimises the float64 GMRES iterations of the
+    resistance problem on held-out configurations."""
+    table = {om: [] for om in omegas}
+    base = []
+    for sd in seeds:
+        wk = make_workload(workload, seed=sd)
+        sph = bie.Spheres(wk["centres"], p, near_gap=1.0)
+        base.append(sph.solve_resistance(wk["v"], wk["omega"], tol=1e-8, precond=bie.PC_M0)[-1]["iters"])
+        for om in omegas:
+            sph.load_precond(scaled(w, om))
+            table[om].append(sph.solve_resistance(wk["v"], wk["omega"], tol=1e-8, precond=bie.PC_MLP)[-1]["iters"])
+        sph.close()
+    best = min(omegas, key=lambda om: (sum(table[om]), om))
+    if log:
+        log(f"M0 iterations {base}; with the learned correction: " +
+            ", ".join(f"omega {om}: {table[om]}" for om in omegas) + f"; chosen {best}")
+    return best, {str(k): v for k, v in table.items()}, base
+
+
 def save_weights(path, w, meta):
     os.makedirs(os.path.dirname(path), exist_ok=True)
     np.savez(path, weights=np.asarray(w, np.float32), meta=np.array(json.dumps(meta)))
@@ -94,6 +129,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--select", type=int, default=4, help="held-out configurations for choosing the relaxation")
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     args = ap.parse_args()
     train = build_set(args.configs, args.rhs, args.p, seed0=1000)
@@ -105,11 +141,13 @@ def main():
     t_train = time.time() - t0
     l1, _ = hold.eval(w)
     ltr, _ = train.eval(w)
+    omega, table, base = select_relaxation(w, args.p, seeds=[600000 + k for k in range(args.select)])
     meta = dict(version=1, formulation="DN_BIE", p=args.p, hidden=HIDDEN, nfeat=bie.NFEAT, nout=278,
                 configs=args.configs, rhs=args.rhs, epochs=args.epochs, lr=args.lr, batch=args.batch,
                 train_loss=float(ltr), holdout_loss_init=float(l0), holdout_loss=float(l1),
-                train_seconds=t_train)
-    save_weights(args.out, w, meta)
+                train_seconds=t_train, relaxation=omega, relaxation_scan=table, m0_iters=base,
+                note="output layer scaled by the relaxation")
+    save_weights(args.out, scaled(w, omega), meta)
     print(json.dumps(dict(meta, loss_hist_first=float(hist[0]), loss_hist_last=float(hist[-1]))))
 
 

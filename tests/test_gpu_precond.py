@@ -150,3 +150,47 @@ def test_nonfinite_weights_are_rejected(cluster):
     w[5] = np.nan
     with pytest.raises(B.BieError):
         s.load_precond(w)
+
+
+def test_trained_network_gain_over_m0():
+    # committed weights (paper_1707_06551_amd/weights/precond_dn.npz, trained on the GPU
+    # from plain float64 solves of 64-sphere, p = 16 configurations); held-out seeds
+    # that neither training, validation nor the relaxation choice used
+    from paper_1707_06551_amd.inputs import make_workload
+    from paper_1707_06551_amd.precond_train import load_weights
+    B = _bie()
+    w, meta = load_weights()
+    m0, ml, mix = [], [], []
+    for sd in (700000, 700001):
+        wk = make_workload("spheres64_p16_train", seed=sd)
+        s = B.Spheres(wk["centres"], 16, near_gap=1.0)
+        s.load_precond(w)
+        F0, T0, _, i0 = s.solve_resistance(wk["v"], wk["omega"], tol=1e-8, precond=B.PC_M0)
+        F1, T1, _, i1 = s.solve_resistance(wk["v"], wk["omega"], tol=1e-8, precond=B.PC_MLP)
+        F2, T2, _, i2 = s.solve_resistance(wk["v"], wk["omega"], tol=1e-8, precision=B.MIXED, precond=B.PC_MLP)
+        assert i0["converged"] and i1["converged"] and i2["converged"]
+        assert i1["fallback_used"] == 0
+        assert rel_err(F1, F0) < 1e-6 and rel_err(F2, F0) < 1e-6
+        m0.append(i0["iters"])
+        ml.append(i1["iters"])
+        mix.append(i2["iters"])
+        s.close()
+    print(f"GMRES iterations M0 {m0}, learned {ml}, mixed+learned {mix}")
+    assert sum(ml) <= 0.9 * sum(m0), (m0, ml)
+
+
+def test_bad_network_falls_back_to_plain_gmres():
+    # a network scaled far beyond its relaxation stalls the preconditioned solve; the
+    # solver must notice, restart plain float64 GMRES from the current iterate, converge
+    from paper_1707_06551_amd.inputs import make_workload
+    from paper_1707_06551_amd.precond_train import load_weights, scaled
+    B = _bie()
+    w, meta = load_weights()
+    wk = make_workload("spheres64_p16_train", seed=700002)
+    s = B.Spheres(wk["centres"], 8, near_gap=1.0)
+    s.load_precond(scaled(w, 200.0))
+    F, T, _, info = s.solve_resistance(wk["v"], wk["omega"], tol=1e-8, precond=B.PC_MLP, max_iter=2000)
+    F0, T0, _, i0 = s.solve_resistance(wk["v"], wk["omega"], tol=1e-8, precond=B.PC_NONE)
+    assert info["converged"] and info["fallback_used"] == 1, info
+    assert rel_err(F, F0) < 1e-6
+    s.close()
