@@ -16,8 +16,14 @@
 //   d = p . o,  r.r = (|p|^2 + 1) - 2 d,  r.n_y = r.o = d - 1,  r.q = p.q - o.q.
 // The sums over a source sphere are kept as  C = sum c_y,  Co = sum c_y o_y,  Q = sum q_y / r
 // so that  sum c_y r_y = p C - Co.  For the allowed (far) pairs r >= d* so the
-// cancellation in r.r costs a few ulp at most.  Per pair: S+D 20 VALU + 1 rsqrt, D 17,
-// S 17.  Self and near source spheres are skipped through a per-target bit mask (a whole
+// cancellation in r.r costs a few ulp at most.  For S+D the double-layer factor
+// 1 + 6 (r.n)/r^2 is rewritten with r.n = d - 1 = (|p|^2 - 1 - r.r)/2 as
+// 3 (|p|^2 - 1)/r^2 - 2, one fused multiply-add per pair with 3 (|p|^2 - 1) formed once
+// per (target, source sphere); the factor stays near 1 (|p| <= r + 1), so this costs no
+// cancellation.  Per pair: S+D 19 VALU + 1 rsqrt, D 17, S 17.  All inner-loop operands
+// are VGPRs, literals or inline constants: on gfx950 a float32 VALU instruction with an
+// SGPR operand issues at half the rate of one without (measured), which is why float32
+// sources are staged in LDS rather than read through the scalar cache.  Self and near source spheres are skipped through a per-target bit mask (a whole
 // wave skips when all its lanes are excluded); per-sphere partial sums are added to the
 // running total with Kahan compensation.  The completion flow of the resistance problem
 // (Stokeslet + rotlet at every centre, Eqs. 5.18-5.19) is added once per (target, sphere)
@@ -62,9 +68,9 @@ struct R4 {
 // KIND: 1 = Stokeslet, 2 = double layer, 3 = Stokeslet + double layer.  Constants:
 //   S:   (1/8pi) [q/r + r (r.q)/r^3]            -> c = (r.q) / r^3
 //   D:   (3/4pi) r (r.q)(r.n)/r^5               -> c = (r.q)(r.n) / r^5
-//   S+D: (1/8pi) [q/r + r (r.q)/r^3 (1 + 6 (r.n)/r^2)]
+//   S+D: (1/8pi) [q/r + r (r.q)/r^3 (1 + 6 (r.n)/r^2)]  -> c = (r.q)/r^3 (3 (|p|^2 - 1)/r^2 - 2)
 template <typename R, int KIND>
-__device__ __forceinline__ void pair(R px, R py, R pz, R K, const R4<R>& o, const R4<R>& q, R& C, R& Cx, R& Cy,
+__device__ __forceinline__ void pair(R px, R py, R pz, R K, R K3, const R4<R>& o, const R4<R>& q, R& C, R& Cx, R& Cy,
                                      R& Cz, R& Qx, R& Qy, R& Qz) {
   const R d = fma(pz, o.z, fma(py, o.y, px * o.x));
   const R r2 = fma((R)-2, d, K);
@@ -78,8 +84,7 @@ __device__ __forceinline__ void pair(R px, R py, R pz, R K, const R4<R>& o, cons
     const R rn = d - (R)1;
     c = (rq * rn) * (ir2 * ir2 * ir);
   } else {
-    const R e = fma(d, (R)6, (R)-6);
-    const R t = fma(e, ir2, (R)1);
+    const R t = fma(K3, ir2, (R)-2);   // 1 + 6 (r.n)/r^2 with K3 = 3 (|p|^2 - 1)
     c = ((rq * ir) * ir2) * t;
   }
   C += c;
@@ -145,7 +150,7 @@ __global__ __launch_bounds__(256) void far_kernel(FarParams a) {
       for (int i = tid; i < P; i += 256) qs[i] = qg[(int64_t)s * P + i];
     }
     const double csx = a.centres4[4 * s], csy = a.centres4[4 * s + 1], csz = a.centres4[4 * s + 2];
-    R px[TPL], py[TPL], pz[TPL], K[TPL];
+    R px[TPL], py[TPL], pz[TPL], K[TPL], K3[TPL];
     bool skip[TPL];
     bool any = false;
 #pragma unroll
@@ -159,6 +164,7 @@ __global__ __launch_bounds__(256) void far_kernel(FarParams a) {
       py[k] = (R)dy + oxt[k][1];
       pz[k] = (R)dz + oxt[k][2];
       K[k] = fma(px[k], px[k], fma(py[k], py[k], fma(pz[k], pz[k], (R)1)));
+      K3[k] = (R)3 * fma(px[k], px[k], fma(py[k], py[k], fma(pz[k], pz[k], (R)-1)));
       any = any || !skip[k];
       if (a.completion && valid[k]) {
         // Stokeslet of strength F_s and rotlet of torque T_s at c_s, in float64
@@ -179,7 +185,10 @@ __global__ __launch_bounds__(256) void far_kernel(FarParams a) {
     R C[TPL], Cx[TPL], Cy[TPL], Cz[TPL], Qx[TPL], Qy[TPL], Qz[TPL];
 #pragma unroll
     for (int k = 0; k < TPL; ++k) C[k] = Cx[k] = Cy[k] = Cz[k] = Qx[k] = Qy[k] = Qz[k] = 0;
-#pragma unroll 4
+    // source unroll: 2 for the float32 S+D kernel (95 VGPRs, 5 waves per SIMD; 4 needs
+    // 117 VGPRs and was 8% slower), 4 elsewhere (equal or better there, measured)
+    constexpr int UNR = (sizeof(R) == 4 && KIND == 3) ? 2 : 4;
+#pragma unroll UNR
     for (int i = 0; i < P; ++i) {
       R4<R> o, qq;
       if (SRC == 0) {
@@ -193,7 +202,7 @@ __global__ __launch_bounds__(256) void far_kernel(FarParams a) {
       }
 #pragma unroll
       for (int k = 0; k < TPL; ++k)
-        pair<R, KIND>(px[k], py[k], pz[k], K[k], o, qq, C[k], Cx[k], Cy[k], Cz[k], Qx[k], Qy[k], Qz[k]);
+        pair<R, KIND>(px[k], py[k], pz[k], K[k], K3[k], o, qq, C[k], Cx[k], Cy[k], Cz[k], Qx[k], Qy[k], Qz[k]);
     }
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
@@ -227,13 +236,14 @@ __global__ void reduce_partials(const double* partial, int nsplit, int64_t n3, d
   }
 }
 
-// Measured on MI355X (512 spheres, p = 12, S+D): float32 LDS 11.4 ms vs scalar 13.8 ms;
-// float64 LDS 22.4 ms vs scalar 21.0 ms.  float32 stages sources in LDS, float64 reads
-// them through the scalar cache.
+// Measured on MI355X (512 spheres, p = 12, S+D, 20-VALU pair form): float32 LDS 11.4 ms
+// vs scalar 13.8 ms; float64 LDS 22.4 ms vs scalar 21.0 ms.  float32 stages sources in
+// LDS, float64 reads them through the scalar cache (float64 VALU issues at one rate
+// with or without SGPR operands).
 template <typename R, int KIND>
 static void far_launch(bie_ctx* c, const FarParams& a, dim3 grid) {
   constexpr int TPL = 2;
-  if (sizeof(R) == 8) {
+  if constexpr (sizeof(R) == 8) {
     far_kernel<R, KIND, TPL, 1><<<grid, dim3(256), 0, c->stream>>>(a);
   } else {
     const size_t sm = 2 * (size_t)c->P * sizeof(R4<R>);
