@@ -107,6 +107,8 @@ def main():
     ap.add_argument("--workload", default="spheres512_p12")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain float64 reference solve")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (HBM byte-counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
@@ -114,6 +116,16 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.calibrate_copy:
+        # a copy of known size: 1 GiB read + 1 GiB written per dispatch
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": 2 * a.numel() * 4, "dispatches": 3}))
+        return
 
     from paper_1707_06551_amd import bie
     from paper_1707_06551_amd.inputs import make_workload
