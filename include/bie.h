@@ -118,13 +118,27 @@ int bie_vsh_inverse(bie_ctx* ctx, int precision, const double* coef, double* u);
 #define BIE_PC_NONE 0 /* no preconditioner                                             */
 #define BIE_PC_M0 1   /* exact inverse of every sphere's isolated self operator        */
 #define BIE_PC_MLP 2  /* M0 plus the learned close-pair coarse correction              */
+/* Flag, OR-ed with BIE_PC_M0 or BIE_PC_MLP: global rigid-mode coarse correction of the
+ * resistance form (no counterpart in the paper).  After the base preconditioner z0 =
+ * M r, z = z0 + P (y - R z0) with M_RPY S y = R r: R projects each sphere's field onto
+ * its six rigid modes (W_1, X_1 of Definition 2.2; a = int f / 4 pi, b = 3 int x x f /
+ * 8 pi), P (a, b) = a + b x x, S = diag(4 pi, 8 pi / 3) turns them into the force and
+ * torque the completion flow of Eqs. 5.18-5.19 carries, and M_RPY is the Rotne-Prager-
+ * Yamakawa grand mobility of the unit spheres (translation (1/8 pi d)[(1 + 2/(3d^2)) I +
+ * (1 - 2/d^2) e e], coupling -[r]_x / (8 pi d^3), rotation -(I - 3 e e)/(16 pi d^3),
+ * self blocks I/6pi and I/8pi).  The coarse system is solved on the device by Jacobi-
+ * preconditioned conjugate gradients (float64, relative residual 1e-7, at most 400
+ * iterations) with a matrix-free all-pairs product over the centres.  n_b <= 65536
+ * (BIE_EINVAL beyond).  The mobility form ignores the flag (its rigid motions are
+ * unknowns with their own rows). */
+#define BIE_PC_RIGID 0x10
 
 typedef struct {
   double tol;        /* stop when ||b - A x||_2 <= tol ||b||_2 (true residual)         */
   int restart;       /* Krylov dimension per cycle (<= 0 selects 100)                    */
   int max_iter;      /* total inner iterations (<= 0 selects 1000)                      */
   int precision;     /* BIE_FP64 or BIE_MIXED                                           */
-  int precond;       /* BIE_PC_*                                                        */
+  int precond;       /* BIE_PC_NONE, _M0 or _MLP, optionally | BIE_PC_RIGID             */
   double inner_tol;  /* BIE_MIXED inner tolerance (<= 0 selects 1e-4)                   */
 } bie_solve_opts;
 

@@ -17,6 +17,7 @@ OP_S, OP_D, OP_SD_BIE, OP_DN_BIE, OP_MOBILITY = 1, 2, 3, 4, 5
 STAGE_SELF, STAGE_NEAR, STAGE_FAR = 0x100, 0x200, 0x400
 FP64, MIXED = 0, 1
 PC_NONE, PC_M0, PC_MLP = 0, 1, 2
+PC_RIGID = 0x10   # flag: global rigid-mode coarse correction (resistance form)
 OK, ENOCONV, EINVAL, EOVERLAP, EDEVICE, ENOMEM = 0, 1, -1, -2, -3, -4
 
 EXPORTED = [

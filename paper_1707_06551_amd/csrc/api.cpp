@@ -103,21 +103,28 @@ void apply_precond(bie_ctx* c, int op_base, int precision, int precond, const do
     throw Error{BIE_EINVAL, "preconditioners exist for BIE_OP_DN_BIE and BIE_OP_MOBILITY"};
   if (precision != BIE_FP64 && precision != BIE_MIXED) throw Error{BIE_EINVAL, "bad precision"};
   const int64_t n = 3 * c->N + (op_base == BIE_OP_MOBILITY ? 6 * c->nb : 0);
-  switch (precond) {
+  const bool rigid = (precond & BIE_PC_RIGID) != 0;
+  const int base = precond & ~BIE_PC_RIGID;
+  if (rigid && base == BIE_PC_NONE) throw Error{BIE_EINVAL, "BIE_PC_RIGID needs BIE_PC_M0 or BIE_PC_MLP"};
+  if (rigid && c->nb > RIGID_MAX_SPHERES) throw Error{BIE_EINVAL, "BIE_PC_RIGID: too many spheres for the coarse solve"};
+  switch (base) {
     case BIE_PC_NONE:
       dev_copy(c, r, z, n);
       return;
     case BIE_PC_M0:
       dev_precond_m0(c, op_base, precision, r, z);
-      return;
+      break;
     case BIE_PC_MLP:
       if (!c->theta_ready) throw Error{BIE_EINVAL, "BIE_PC_MLP needs bie_precond_load first"};
       dev_precond_m0(c, op_base, precision, r, z);
       if (op_base == BIE_OP_DN_BIE) coarse_correct(c, r, z);
-      return;
+      break;
     default:
       throw Error{BIE_EINVAL, "unknown preconditioner"};
   }
+  // the mobility form carries the rigid motions as unknowns with their own rows; the
+  // global coarse correction applies to the resistance form only
+  if (rigid && op_base == BIE_OP_DN_BIE) rigid_correct(c, r, z);
 }
 
 }  // namespace bie

@@ -100,6 +100,12 @@ struct bie_ctx {
   bie::DevBuf mlp_theta;            // near pairs x 278 float: MLP output
   bie::DevBuf rho, zeta;            // nb x 25 double
   bool theta_ready = false;
+
+  // global rigid-mode coarse correction (rigid.hip), allocated on first use
+  bie::DevBuf rg_vec;               // 8 x 6 nb double: R r, R z, CG vectors, solution
+  bie::DevBuf rg_partial;           // source splits x 6 nb double: mobility product partials
+  bie::DevBuf rg_dots, rg_hist;     // block partial sums; CG scalars per iteration
+  int rg_last_iters = 0;            // CG iterations of the last coarse solve
 };
 
 namespace bie {
@@ -139,6 +145,10 @@ void build_coarse(bie_ctx* c);
 void lowmode_restrict(bie_ctx* c, const double* f, double* rho);
 void lowmode_prolong(bie_ctx* c, const double* rho, double* f, bool accumulate);
 void coarse_correct(bie_ctx* c, const double* r, double* z);
+
+// global rigid-mode coarse correction: z <- z + P (A_c^-1 R r - R z)
+constexpr int64_t RIGID_MAX_SPHERES = 65536;
+void rigid_correct(bie_ctx* c, const double* r, double* z);
 int64_t mlp_n_weights();
 double mlp_eval(const bie_mlp_data* d, const float* weights, float* grad);
 void mlp_train(const bie_mlp_data* d, float* weights, int epochs, int cfg_per_batch, double lr, double* loss_hist);

@@ -272,8 +272,11 @@ int solve(bie_ctx* c, int op, const double* b, double* x, int64_t n, const bie_s
   if (o.max_iter <= 0) o.max_iter = 1000;
   if (!(o.inner_tol > 0)) o.inner_tol = 1e-4;
   if (o.restart > 500) throw Error{BIE_EINVAL, "restart must be <= 500"};
-  if (o.precond == BIE_PC_MLP && !c->theta_ready) throw Error{BIE_EINVAL, "BIE_PC_MLP needs bie_precond_load first"};
-  if (o.precond < BIE_PC_NONE || o.precond > BIE_PC_MLP) throw Error{BIE_EINVAL, "unknown preconditioner"};
+  const int pc_base = o.precond & ~BIE_PC_RIGID;
+  if (pc_base == BIE_PC_MLP && !c->theta_ready) throw Error{BIE_EINVAL, "BIE_PC_MLP needs bie_precond_load first"};
+  if (pc_base < BIE_PC_NONE || pc_base > BIE_PC_MLP) throw Error{BIE_EINVAL, "unknown preconditioner"};
+  if ((o.precond & BIE_PC_RIGID) && pc_base == BIE_PC_NONE)
+    throw Error{BIE_EINVAL, "BIE_PC_RIGID needs BIE_PC_M0 or BIE_PC_MLP"};
   const int m = o.restart;
   const bool flexible = o.precond != BIE_PC_NONE;
   // work space
