@@ -119,8 +119,9 @@ int bie_vsh_inverse(bie_ctx* ctx, int precision, const double* coef, double* u);
 #define BIE_PC_M0 1   /* exact inverse of every sphere's isolated self operator        */
 #define BIE_PC_MLP 2  /* M0 plus the learned close-pair coarse correction              */
 /* Flag, OR-ed with BIE_PC_M0 or BIE_PC_MLP: global rigid-mode coarse correction of the
- * resistance form (no counterpart in the paper).  After the base preconditioner z0 =
- * M r, z = z0 + P (y - R z0) with M_RPY S y = R r: R projects each sphere's field onto
+ * resistance form (no counterpart in the paper).  With z0 = M0 r, z = z0 + P (y - R z0)
+ * with M_RPY S y = R r (with BIE_PC_MLP the learned correction is then added to z, so
+ * weights for this combination are trained on that base): R projects each sphere's field onto
  * its six rigid modes (W_1, X_1 of Definition 2.2; a = int f / 4 pi, b = 3 int x x f /
  * 8 pi), P (a, b) = a + b x x, S = diag(4 pi, 8 pi / 3) turns them into the force and
  * torque the completion flow of Eqs. 5.18-5.19 carries, and M_RPY is the Rotne-Prager-

@@ -117,14 +117,17 @@ void apply_precond(bie_ctx* c, int op_base, int precision, int precond, const do
     case BIE_PC_MLP:
       if (!c->theta_ready) throw Error{BIE_EINVAL, "BIE_PC_MLP needs bie_precond_load first"};
       dev_precond_m0(c, op_base, precision, r, z);
-      if (op_base == BIE_OP_DN_BIE) coarse_correct(c, r, z);
       break;
     default:
       throw Error{BIE_EINVAL, "unknown preconditioner"};
   }
-  // the mobility form carries the rigid motions as unknowns with their own rows; the
-  // global coarse correction applies to the resistance form only
-  if (rigid && op_base == BIE_OP_DN_BIE) rigid_correct(c, r, z);
+  // Both corrections act on the resistance form only (the mobility form carries the
+  // rigid motions as unknowns with their own rows).  The global rigid-mode correction
+  // resets the rigid part of M0 r; the learned close-pair correction is added after it,
+  // so that a network trained on that base keeps its rigid-mode output.
+  if (op_base != BIE_OP_DN_BIE) return;
+  if (rigid) rigid_correct(c, r, z);
+  if (base == BIE_PC_MLP) coarse_correct(c, r, z);
 }
 
 }  // namespace bie

@@ -3,14 +3,15 @@
 Data: for each training configuration (seeded placements of the 64-sphere training
 workload), random low-mode right-hand sides b = P xi (xi ~ N(0, 1), 25 coefficients per
 sphere) are solved with the plain float64 method (A x = b, completed double-layer
-form); the target is t = R x - R M0 b, the part of the low-mode response that the
-isolated-sphere inverse M0 misses.  Training runs on the GPU in the library's own
-forward / backward / Adam kernels (bie_mlp_train).  Applied at full strength the
-additive correction over-corrects, so a relaxation omega (theta -> omega theta) is
-chosen on held-out configurations by GMRES iteration count and folded into the saved
-output layer.
+form); the target is t = R x - R B b, the part of the low-mode response that the base
+preconditioner B misses: the isolated-sphere inverse M0 (--base m0), or M0 followed by
+the global rigid-mode coarse correction (--base m0r, BIE_PC_RIGID).  Training runs on
+the GPU in the library's own forward / backward / Adam kernels (bie_mlp_train).
+Applied at full strength the additive correction over-corrects, so a relaxation omega
+(theta -> omega theta) is chosen on held-out configurations by GMRES iteration count
+and folded into the saved output layer.
 
-Usage: python -m paper_1707_06551_amd.precond_train --configs 200 --rhs 4 --p 16 --epochs 300
+Usage: python -m paper_1707_06551_amd.precond_train --configs 200 --rhs 4 --p 16 --epochs 400 [--base m0r]
 """
 import argparse
 import json
@@ -43,7 +44,11 @@ def init_weights(seed=0, out_scale=1e-3):
     return w
 
 
-def config_samples(sph, n_rhs, rng, tol=1e-8):
+BASES = {"m0": bie.PC_M0, "m0r": bie.PC_M0 | bie.PC_RIGID}
+DEFAULT_FILES = {"m0": DEFAULT_WEIGHTS, "m0r": os.path.join(HERE, "weights", "precond_dn_rigid.npz")}
+
+
+def config_samples(sph, n_rhs, rng, tol=1e-8, base=bie.PC_M0):
     """(xi, target) of one configuration: (nb, n_rhs, 25) each, plus solve statistics."""
     import torch
     xi = rng.standard_normal((sph.nb, n_rhs, bie.NLOW))
@@ -52,25 +57,25 @@ def config_samples(sph, n_rhs, rng, tol=1e-8):
     for r in range(n_rhs):
         rho = torch.from_numpy(np.ascontiguousarray(xi[:, r, :]).reshape(-1)).cuda()
         b = sph.lowmodes_synth(rho)
-        x, info = sph.solve(bie.OP_DN_BIE, b, tol=tol, precision=bie.FP64, precond=bie.PC_M0)
+        x, info = sph.solve(bie.OP_DN_BIE, b, tol=tol, precision=bie.FP64, precond=base)
         if not info["converged"]:
             raise RuntimeError(f"training solve did not converge: {info}")
         iters.append(info["iters"])
-        z0 = sph.apply_precond(bie.OP_DN_BIE, b, precond=bie.PC_M0)
+        z0 = sph.apply_precond(bie.OP_DN_BIE, b, precond=base)
         t = sph.lowmodes(x) - sph.lowmodes(z0)
         torch.cuda.synchronize()
         target[:, r, :] = t.cpu().numpy().reshape(sph.nb, bie.NLOW)
     return xi, target, iters
 
 
-def build_set(n_configs, n_rhs, p, seed0=1000, workload="spheres64_p16_train", log=print):
+def build_set(n_configs, n_rhs, p, seed0=1000, workload="spheres64_p16_train", log=print, base=bie.PC_M0):
     ts = bie.TrainingSet(n_rhs)
     t0 = time.time()
     for k in range(n_configs):
         w = make_workload(workload, seed=seed0 + k)
         sph = bie.Spheres(w["centres"], p, near_gap=1.0)
         pi, pj, feats, frames = sph.pair_geometry()
-        xi, target, iters = config_samples(sph, n_rhs, np.random.default_rng(seed0 + k + 7919))
+        xi, target, iters = config_samples(sph, n_rhs, np.random.default_rng(seed0 + k + 7919), base=base)
         ts.add(pi, pj, feats, frames, xi, target)
         sph.close()
         if log and (k % 20 == 0 or k == n_configs - 1):
@@ -89,25 +94,26 @@ def scaled(w, omega):
 
 
 def select_relaxation(w, p, seeds, omegas=(0.1, 0.15, 0.2, 0.25, 0.3, 0.4, 0.6, 1.0), workload="spheres64_p16_train",
-                      log=print):
+                      log=print, base=bie.PC_M0):
     """The additive correction over-corrects at full strength; choose the relaxation
     omega (theta -> omega theta) that minimises the float64 GMRES iterations of the
     resistance problem on held-out configurations."""
     table = {om: [] for om in omegas}
-    base = []
+    base_its = []
     for sd in seeds:
         wk = make_workload(workload, seed=sd)
         sph = bie.Spheres(wk["centres"], p, near_gap=1.0)
-        base.append(sph.solve_resistance(wk["v"], wk["omega"], tol=1e-8, precond=bie.PC_M0)[-1]["iters"])
+        base_its.append(sph.solve_resistance(wk["v"], wk["omega"], tol=1e-8, precond=base)[-1]["iters"])
         for om in omegas:
             sph.load_precond(scaled(w, om))
-            table[om].append(sph.solve_resistance(wk["v"], wk["omega"], tol=1e-8, precond=bie.PC_MLP)[-1]["iters"])
+            table[om].append(sph.solve_resistance(wk["v"], wk["omega"], tol=1e-8,
+                                                  precond=bie.PC_MLP | (base & bie.PC_RIGID))[-1]["iters"])
         sph.close()
     best = min(omegas, key=lambda om: (sum(table[om]), om))
     if log:
-        log(f"M0 iterations {base}; with the learned correction: " +
+        log(f"base iterations {base_its}; with the learned correction: " +
             ", ".join(f"omega {om}: {table[om]}" for om in omegas) + f"; chosen {best}")
-    return best, {str(k): v for k, v in table.items()}, base
+    return best, {str(k): v for k, v in table.items()}, base_its
 
 
 def save_weights(path, w, meta):
@@ -130,10 +136,14 @@ def main():
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--select", type=int, default=4, help="held-out configurations for choosing the relaxation")
-    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--base", choices=sorted(BASES), default="m0",
+                    help="preconditioner the correction is trained on top of (m0r: M0 + BIE_PC_RIGID)")
+    ap.add_argument("--out", default=None)
     args = ap.parse_args()
-    train = build_set(args.configs, args.rhs, args.p, seed0=1000)
-    hold = build_set(args.holdout, args.rhs, args.p, seed0=900000)
+    base = BASES[args.base]
+    out = args.out or DEFAULT_FILES[args.base]
+    train = build_set(args.configs, args.rhs, args.p, seed0=1000, base=base)
+    hold = build_set(args.holdout, args.rhs, args.p, seed0=900000, base=base)
     w0 = init_weights(0)
     l0, _ = hold.eval(w0)
     t0 = time.time()
@@ -141,13 +151,13 @@ def main():
     t_train = time.time() - t0
     l1, _ = hold.eval(w)
     ltr, _ = train.eval(w)
-    omega, table, base = select_relaxation(w, args.p, seeds=[600000 + k for k in range(args.select)])
-    meta = dict(version=1, formulation="DN_BIE", p=args.p, hidden=HIDDEN, nfeat=bie.NFEAT, nout=278,
+    omega, table, base_its = select_relaxation(w, args.p, seeds=[600000 + k for k in range(args.select)], base=base)
+    meta = dict(version=1, formulation="DN_BIE", base=args.base, p=args.p, hidden=HIDDEN, nfeat=bie.NFEAT, nout=278,
                 configs=args.configs, rhs=args.rhs, epochs=args.epochs, lr=args.lr, batch=args.batch,
                 train_loss=float(ltr), holdout_loss_init=float(l0), holdout_loss=float(l1),
-                train_seconds=t_train, relaxation=omega, relaxation_scan=table, m0_iters=base,
+                train_seconds=t_train, relaxation=omega, relaxation_scan=table, base_iters=base_its,
                 note="output layer scaled by the relaxation")
-    save_weights(args.out, scaled(w, omega), meta)
+    save_weights(out, scaled(w, omega), meta)
     print(json.dumps(dict(meta, loss_hist_first=float(hist[0]), loss_hist_last=float(hist[-1]))))
 
 

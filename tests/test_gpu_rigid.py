@@ -64,8 +64,8 @@ def test_rigid_correction_on_the_learned_preconditioner():
     xh, wq = g.grid["xhat"], g.grid["wnode"]
     rho = np.stack([coarse.restrict(r[g.sphere_nodes(k)], xh, wq) for k in range(g.nb)])
     zeta = coarse.coarse_apply(pairs, dirs, theta, rho)
-    z0 = m0_resistance(g, r) + np.concatenate([coarse.prolong(zeta[k], xh) for k in range(g.nb)])
-    ref = rigid.correct(g, r, z0)
+    # the rigid correction resets the rigid part of M0 r, the learned one is added after it
+    ref = rigid.correct(g, r, m0_resistance(g, r)) + np.concatenate([coarse.prolong(zeta[k], xh) for k in range(g.nb)])
     assert rel_err(z, ref) < 1e-5, rel_err(z, ref)
     s.close()
 
@@ -124,3 +124,27 @@ def test_rigid_correction_gain_on_a_dilute_suspension():
     print(f"GMRES iterations: M0 {i0['iters']}, M0 + rigid {i1['iters']}, mixed M0 + rigid {i2['iters']}")
     assert i1["iters"] <= 0.7 * i0["iters"], (i0["iters"], i1["iters"])
     s.close()
+
+
+def test_network_trained_on_the_rigid_base_gains_over_it():
+    # committed weights (paper_1707_06551_amd/weights/precond_dn_rigid.npz) trained with
+    # base M0 + BIE_PC_RIGID on 64-sphere, p = 16 configurations; held-out seeds
+    from paper_1707_06551_amd.inputs import make_workload
+    from paper_1707_06551_amd.precond_train import DEFAULT_FILES, load_weights
+    B = _bie()
+    w, meta = load_weights(DEFAULT_FILES["m0r"])
+    assert meta["base"] == "m0r"
+    base, learned = [], []
+    for sd in (700000, 700001):
+        wk = make_workload("spheres64_p16_train", seed=sd)
+        s = B.Spheres(wk["centres"], 16, near_gap=1.0)
+        s.load_precond(w)
+        F0, T0, _, i0 = s.solve_resistance(wk["v"], wk["omega"], tol=1e-8, precond=B.PC_M0 | B.PC_RIGID)
+        F1, T1, _, i1 = s.solve_resistance(wk["v"], wk["omega"], tol=1e-8, precond=B.PC_MLP | B.PC_RIGID)
+        assert i0["converged"] and i1["converged"] and i1["fallback_used"] == 0
+        assert rel_err(F1, F0) < 1e-6 and rel_err(T1, T0) < 1e-6
+        base.append(i0["iters"])
+        learned.append(i1["iters"])
+        s.close()
+    print(f"GMRES iterations M0 + rigid {base}, + learned {learned}")
+    assert sum(learned) <= 0.92 * sum(base), (base, learned)
