@@ -94,9 +94,16 @@ def cpu_baseline(w, seconds_target=15.0):
             nt += tg.size
             pairs += int(allowed_per_t[g.sphere_of[tg]].sum()) * g.P
         dt = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return dict(value=pairs / dt, unit="pair-interactions/s", cores=1, kind="oracle",
                 sample=f"far-field S+D direct sum for {nt} random target nodes x all sources of "
-                       f"{w['name']} ({pairs:.3e} pairs, {dt:.1f} s, numpy float64, 1 thread)")
+                       f"{w['name']} ({pairs:.3e} pairs, {dt:.1f} s, numpy float64, 1 thread)",
+                host_cpus=os.cpu_count(), cpu_model=model)
 
 
 def main():

@@ -114,3 +114,14 @@ def slip_field(slip_coef, normals, sphere_of):
 def random_density(n_nodes, rng):
     """A random node density (N, 3) ~ N(0, 1) for matvec parity tests."""
     return rng.standard_normal((n_nodes, 3))
+
+
+def lattice_centres(units, q):
+    """Centres of the monodisperse cubic lattice of the scaling experiment (Section 6,
+    Fig. 8 (a), (b)) rescaled to unit spheres: (units + 1)^3 spheres on the vertices of
+    a cubic grid of spacing 2 / (1 - 2^-q) (radius 1 - 2^-q at spacing 2 in the paper's
+    units): spacing 4 (q = 1, loosely packed) or 32/15 (q = 4, densely packed, gap 2/15)."""
+    h = 2.0 / (1.0 - 2.0 ** (-q))
+    g = np.arange(units + 1, dtype=np.float64) * h
+    x, y, z = np.meshgrid(g, g, g, indexing="ij")
+    return np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)

@@ -1,0 +1,63 @@
+"""GPU parity on the cubic lattices of the scaling experiment (Section 6, Fig. 8): the
+full operator on a 27-sphere densely packed lattice (every sphere has face neighbours
+at gap 2/15 inside the near zone) against the oracle, and sampled targets of the
+largest lattice (4913 spheres, p = 8) in the launch configuration run_lattice times."""
+import numpy as np
+import pytest
+
+from oracle.grid import Geometry
+from oracle.operators import Operators
+from paper_1707_06551_amd.inputs import lattice_centres
+from tests.gpu_common import max_rel, rel_err
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+OPS = {"S": 1, "D": 2, "SD_BIE": 3, "DN_BIE": 4}
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).reshape(-1)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("q", [1, 4])
+@pytest.mark.parametrize("opname", ["D", "DN_BIE"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_lattice_operator_parity(q, opname, precision):
+    from paper_1707_06551_amd import bie
+    c = lattice_centres(2, q)
+    s = bie.Spheres(c, 4, near_gap=1.0)
+    g = Geometry(c, 4, near_gap=1.0)
+    ops = Operators(g)
+    # q = 4: six face neighbours per interior sphere are near; q = 1: none
+    assert (g.near.sum() > 0) == (q == 4)
+    assert sorted(map(tuple, s.near_pairs().T.tolist())) == sorted(map(tuple, np.argwhere(g.near).tolist()))
+    x = np.random.default_rng(7).standard_normal((g.N, 3))
+    out = host(s.apply(OPS[opname], dev(x), precision=precision)).reshape(g.N, 3)
+    ref = ops.apply(opname, x)
+    tol = 1e-11 if precision == 0 else 1e-6
+    assert rel_err(out, ref) < tol, (rel_err(out, ref), max_rel(out, ref))
+    s.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_largest_dense_lattice_sampled(precision):
+    from paper_1707_06551_amd import bie
+    c = lattice_centres(16, 4)
+    s = bie.Spheres(c, 8, near_gap=1.0)
+    g = Geometry(c, 8, near_gap=1.0)
+    ops = Operators(g)
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal((g.N, 3))
+    out = host(s.apply(OPS["D"], dev(x), precision=precision)).reshape(g.N, 3)
+    centre = int(np.argmin(np.linalg.norm(c - c.mean(0), axis=1)))   # six near neighbours
+    tg = np.concatenate([np.arange(centre * g.P, (centre + 1) * g.P), rng.choice(g.N, 48, replace=False)])
+    ref = ops.apply("D", x, targets=tg)
+    tol = 1e-11 if precision == 0 else 1e-6
+    assert rel_err(out[tg], ref) < tol, (rel_err(out[tg], ref), max_rel(out[tg], ref))
+    s.close()
