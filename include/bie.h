@@ -130,7 +130,7 @@ int bie_vsh_inverse(bie_ctx* ctx, int precision, const double* coef, double* u);
  * self blocks I/6pi and I/8pi).  The coarse system is solved on the device by Jacobi-
  * preconditioned conjugate gradients (float64, relative residual 1e-7, at most 400
  * iterations) with a matrix-free all-pairs product over the centres.  n_b <= 65536
- * (BIE_EINVAL beyond).  The mobility form ignores the flag (its rigid motions are
+ * (BIE_EINVAL beyond).  Other forms ignore the flag (the mobility form carries its rigid motions as
  * unknowns with their own rows). */
 #define BIE_PC_RIGID 0x10
 
@@ -170,14 +170,30 @@ int bie_solve_resistance(bie_ctx* ctx, const double* v, const double* omega, con
 int bie_solve_mobility(bie_ctx* ctx, const double* F, const double* T, const double* slip,
                        const bie_solve_opts* opts, double* v, double* omega, double* mu, bie_solve_info* info);
 
-/* Generic solve of op (BIE_OP_DN_BIE or BIE_OP_MOBILITY) with a caller right-hand side:
- * b, x device float64 of length 3N (3N + 6 n_b for mobility).  Same solver and return
- * codes as bie_solve_resistance.  Synchronises the stream. */
+/* Generic solve of op (BIE_OP_DN_BIE, BIE_OP_MOBILITY or BIE_OP_SD_BIE) with a caller
+ * right-hand side: b, x device float64 of length 3N (3N + 6 n_b for mobility).  With
+ * BIE_OP_SD_BIE and b = -u_inf at the nodes this is the porous-media problem (Problem 1,
+ * Eq. 5.4: spheres held fixed in an imposed flow u_inf); the flow is then
+ * u_inf + bie_eval_field(BIE_OP_SD_BIE, x) off the surfaces (Eq. 5.3).  Same solver and
+ * return codes as bie_solve_resistance.  Synchronises the stream. */
 int bie_solve(bie_ctx* ctx, int op, const double* b, double* x, const bie_solve_opts* opts, bie_solve_info* info);
 
-/* z = M r for the preconditioner precond (BIE_PC_*) of op, in the given precision.
+/* z = M r for the preconditioner precond (BIE_PC_*) of op (BIE_OP_DN_BIE,
+ * BIE_OP_MOBILITY or BIE_OP_SD_BIE; for BIE_OP_SD_BIE, M0 inverts 1/2 + S + D_pv of each
+ * isolated sphere and the corrections do not apply), in the given precision.
  * r, z: device float64, length 3N (3N + 6 n_b for mobility), must not alias. */
 int bie_apply_precond(bie_ctx* ctx, int op, int precision, int precond, const double* r, double* z);
+
+/* Velocity at fluid points (the representations of Eqs. 5.3, 5.13 and 5.18 evaluated off
+ * the surfaces): the layer potential of op (BIE_OP_S, BIE_OP_D, BIE_OP_SD_BIE = S + D, or
+ * BIE_OP_DN_BIE = D plus the completion flow of Eqs. 5.18-5.19; the identity term of
+ * the second-kind forms is a surface term and is not added) of the node density mu
+ * (device float64, 3N) at n_targets points (device float64, n_targets x 3, row-major)
+ * -> u (device float64, n_targets x 3).  Per sphere k: |x - c_k| - 1 < near_gap takes the
+ * exterior series of Eqs. 3.6-3.11 (Section 3), otherwise the smooth quadrature of Eq.
+ * 4.4.  Float64.  A point inside or on a sphere gets NaN and the call returns BIE_EINVAL
+ * after writing the others.  n_targets = 0 is a no-op.  Synchronises the stream. */
+int bie_eval_field(bie_ctx* ctx, int op, const double* mu, int64_t n_targets, const double* targets, double* u);
 
 /* ---- learned close-pair coarse correction (no counterpart in the paper) -------------
  * Coarse space per sphere: the vector spherical harmonics of degree <= 2 (Definition

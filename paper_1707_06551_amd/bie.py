@@ -24,7 +24,7 @@ EXPORTED = [
     "bie_build_spheres", "bie_free", "bie_sizes", "bie_get_nodes", "bie_near_pairs", "bie_apply_bio",
     "bie_vsh_forward", "bie_vsh_inverse", "bie_solve_resistance", "bie_solve_mobility", "bie_last_error",
     "bie_solve", "bie_apply_precond", "bie_lowmodes", "bie_lowmodes_synth", "bie_pair_geometry",
-    "bie_mlp_n_weights", "bie_precond_load", "bie_mlp_eval", "bie_mlp_train",
+    "bie_mlp_n_weights", "bie_precond_load", "bie_mlp_eval", "bie_mlp_train", "bie_eval_field",
 ]
 NLOW = 25
 NFEAT = 8
@@ -96,6 +96,8 @@ def lib():
     L.bie_solve.restype = I
     L.bie_apply_precond.argtypes = [VP, I, I, I, VP, VP]
     L.bie_apply_precond.restype = I
+    L.bie_eval_field.argtypes = [VP, I, VP, I64, VP, VP]
+    L.bie_eval_field.restype = I
     L.bie_lowmodes.argtypes = [VP, VP, VP]
     L.bie_lowmodes.restype = I
     L.bie_lowmodes_synth.argtypes = [VP, VP, VP]
@@ -277,6 +279,21 @@ class Spheres:
         z = torch.empty_like(r)
         _check(lib().bie_apply_precond(self._h, op, precision, precond, _dptr(r), _dptr(z)))
         return z
+
+    def eval_field(self, op, mu, targets, u=None):
+        """Layer potential of op (OP_S, OP_D, OP_SD_BIE, OP_DN_BIE) of the node density mu
+        (device, 3N) at fluid points targets ((M, 3) host array or device tensor) ->
+        device tensor (3M)."""
+        import torch
+        if torch.is_tensor(targets):
+            t = targets.contiguous()
+        else:
+            t = torch.from_numpy(np.ascontiguousarray(targets, dtype=np.float64).reshape(-1, 3)).to(mu.device)
+        m = t.numel() // 3
+        if u is None:
+            u = torch.empty(3 * m, dtype=torch.float64, device=mu.device)
+        _check(lib().bie_eval_field(self._h, op, _dptr(mu), m, _dptr(t) if m else None, _dptr(u) if m else None))
+        return u
 
     def lowmodes(self, f):
         import torch

@@ -99,8 +99,8 @@ void dev_precond_m0(bie_ctx* c, int op_base, int precision, const double* r, dou
 }
 
 void apply_precond(bie_ctx* c, int op_base, int precision, int precond, const double* r, double* z) {
-  if (op_base != BIE_OP_DN_BIE && op_base != BIE_OP_MOBILITY)
-    throw Error{BIE_EINVAL, "preconditioners exist for BIE_OP_DN_BIE and BIE_OP_MOBILITY"};
+  if (op_base != BIE_OP_DN_BIE && op_base != BIE_OP_MOBILITY && op_base != BIE_OP_SD_BIE)
+    throw Error{BIE_EINVAL, "preconditioners exist for BIE_OP_DN_BIE, BIE_OP_MOBILITY and BIE_OP_SD_BIE"};
   if (precision != BIE_FP64 && precision != BIE_MIXED) throw Error{BIE_EINVAL, "bad precision"};
   const int64_t n = 3 * c->N + (op_base == BIE_OP_MOBILITY ? 6 * c->nb : 0);
   const bool rigid = (precond & BIE_PC_RIGID) != 0;
@@ -349,8 +349,8 @@ int bie_solve(bie_ctx* c, int op, const double* b, double* x, const bie_solve_op
     bie::set_error("null argument");
     return BIE_EINVAL;
   }
-  if (op != BIE_OP_DN_BIE && op != BIE_OP_MOBILITY) {
-    bie::set_error("bie_solve supports BIE_OP_DN_BIE and BIE_OP_MOBILITY");
+  if (op != BIE_OP_DN_BIE && op != BIE_OP_MOBILITY && op != BIE_OP_SD_BIE) {
+    bie::set_error("bie_solve supports BIE_OP_DN_BIE, BIE_OP_MOBILITY and BIE_OP_SD_BIE");
     return BIE_EINVAL;
   }
   int rc = BIE_OK;
@@ -365,6 +365,15 @@ int bie_apply_precond(bie_ctx* c, int op, int precision, int precond, const doub
     return BIE_EINVAL;
   }
   BIE_TRY(bie::apply_precond(c, op, precision, precond, r, z));
+  return BIE_OK;
+}
+
+int bie_eval_field(bie_ctx* c, int op, const double* mu, int64_t n_targets, const double* targets, double* u) {
+  if (!c) {
+    bie::set_error("null context");
+    return BIE_EINVAL;
+  }
+  BIE_TRY(bie::eval_field(c, op, mu, n_targets, targets, u));
   return BIE_OK;
 }
 

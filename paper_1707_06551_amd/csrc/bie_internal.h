@@ -126,6 +126,7 @@ struct VshCall {
 };
 void launch_vsh(bie_ctx* c, int precision, const VshCall& v);
 void launch_near(bie_ctx* c, const OpSpec& spec, double* u);
+void series_radial(double a_s, double a_d, int p, double* kvv, double* kww, double* kwv, double* kxx);
 void launch_far(bie_ctx* c, int precision, const OpSpec& spec, double* u);
 void apply(bie_ctx* c, int op, int precision, const double* mu, double* u);
 
@@ -149,6 +150,9 @@ void coarse_correct(bie_ctx* c, const double* r, double* z);
 // global rigid-mode coarse correction: z <- z + P (A_c^-1 R r - R z)
 constexpr int64_t RIGID_MAX_SPHERES = 65536;
 void rigid_correct(bie_ctx* c, const double* r, double* z);
+
+// layer potentials at fluid points (field.hip)
+void eval_field(bie_ctx* c, int op_base, const double* mu, int64_t M, const double* x, double* u);
 int64_t mlp_n_weights();
 double mlp_eval(const bie_mlp_data* d, const float* weights, float* grad);
 void mlp_train(const bie_mlp_data* d, float* weights, int epochs, int cfg_per_batch, double lr, double* loss_hist);

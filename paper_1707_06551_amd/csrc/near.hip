@@ -2,15 +2,12 @@
 //
 // For every directed near pair (source s, target t) and every node x of sphere t, the
 // layer potential a_S S[mu_s] + a_D D[mu_s] is evaluated from the V, W, X coefficients of
-// the density of sphere s by the exterior formulas, in float64:
-//   u(x) = sum_{n,m} (fVV_n V^ + fWV_n W^) V_n^m + fWW_n W^ W_n^m + fXX_n X^ X_n^m,
-// with (r, theta, phi) the spherical coordinates of x - c_s and the harmonics evaluated
-// at (theta, phi).  One work-group per target sphere (one thread per target node); the
-// group walks the near list of its sphere, staging each source's coefficients in LDS, so
-// every target is written by exactly one thread (no atomics, deterministic order).
-// Legendre functions at the target are generated by the normalised recurrences in n,
-// using Q = Pbar / sin(theta) for m >= 1 so nothing is divided by sin(theta).
+// the density of sphere s by the exterior formulas, in float64 (series.h).  One
+// work-group per target sphere (one thread per target node); the group walks the near
+// list of its sphere, staging each source's coefficients in LDS, so every target is
+// written by exactly one thread (no atomics, deterministic order).
 #include "bie_internal.h"
+#include "series.h"
 
 namespace bie {
 
@@ -54,116 +51,29 @@ __global__ __launch_bounds__(1024) void near_kernel(NearParams a) {
     const double dx = (ctx - a.centres4[4 * s]) + ox;
     const double dy = (cty - a.centres4[4 * s + 1]) + oy;
     const double dz = (ctz - a.centres4[4 * s + 2]) + oz;
-    const double rho2 = dx * dx + dy * dy;
-    const double r = sqrt(rho2 + dz * dz);
-    const double ir = 1.0 / r;
-    const double ct = dz * ir;
-    const double rho = sqrt(rho2);
-    const double st = rho * ir;
-    double cph = 1.0, sph = 0.0;
-    if (rho > 0.0) {
-      cph = dx / rho;
-      sph = dy / rho;
-    }
-    const double ir2 = ir * ir;
-    double ur = 0, ut = 0, up = 0;
-    double cm = 1.0, sm_ = 0.0;                 // e^{i m phi}
-    double pmm = 0.28209479177387814;            // Pbar_0^0 = 1 / sqrt(4 pi)
-    double qmm = 0.0;
-    double irm = 1.0;                            // r^{-m}
-    for (int m = 0; m <= a.mmax; ++m) {
-      const int off = m * (a.p + 1) - (m * (m - 1)) / 2;
-      if (m > 0) {
-        const double fm = rec[6 * off + 5];
-        qmm = fm * pmm;
-        pmm = fm * st * pmm;
-        const double c2 = cm * cph - sm_ * sph;
-        sm_ = sm_ * cph + cm * sph;
-        cm = c2;
-        irm *= ir;
-      }
-      double srr = 0, sri = 0, str = 0, sti = 0, spr = 0, spi = 0;
-      double rp = irm;  // r^{-n}
-      if (m == 0) {
-        double pm1 = 0.0, p0 = pmm;                           // Pbar_{n-1}^0, Pbar_n^0
-        double z0 = 0.0, z1 = 1.2247448713915890 * pmm;       // Q_n^1, Q_{n+1}^1 (Q_1^1 = sqrt(3/2) Pbar_0^0)
-        for (int n = 0; n <= a.p; ++n) {
-          const double* rc = rec + 6 * n;
-          const double* c0 = cs + 2 * n;
-          const double* c1 = cs + 2 * (nc + n);
-          const double* c2 = cs + 2 * (2 * nc + n);
-          const double fvv = a.kvv[n] * rp * ir2, fww = a.kww[n] * rp;
-          const double fwv = a.kwv[n] * (rp * ir2 - rp), fxx = a.kxx[n] * rp * ir;
-          const double al_r = fvv * c0[0] + fwv * c1[0], al_i = fvv * c0[1] + fwv * c1[1];
-          const double be_r = fww * c1[0], be_i = fww * c1[1];
-          const double ga_r = fxx * c2[0], ga_i = fxx * c2[1];
-          const double yr = -(n + 1.0) * al_r + n * be_r, yi = -(n + 1.0) * al_i + n * be_i;
-          const double gr = al_r + be_r, gi = al_i + be_i;
-          const double D = rc[2] * st * z0;
-          srr += yr * p0;
-          sri += yi * p0;
-          str += gr * D;
-          sti += gi * D;
-          spr += ga_r * D;
-          spi += ga_i * D;
-          const double pn1 = rc[0] * (ct * p0 - rc[1] * pm1);
-          pm1 = p0;
-          p0 = pn1;
-          const double z2 = rc[4] * (ct * z1 - rc[5] * z0);
-          z0 = z1;
-          z1 = z2;
-          rp *= ir;
-        }
-      } else {
-        double qm1 = 0.0, q0 = qmm, q1 = rec[6 * off + 4] * ct * qmm;  // Q_{n-1}, Q_n, Q_{n+1}
-        for (int n = m; n <= a.p; ++n) {
-          const int i = off + (n - m);
-          const double* rc = rec + 6 * i;
-          const double* c0 = cs + 2 * i;
-          const double* c1 = cs + 2 * (nc + i);
-          const double* c2 = cs + 2 * (2 * nc + i);
-          const double fvv = a.kvv[n] * rp * ir2, fww = a.kww[n] * rp;
-          const double fwv = a.kwv[n] * (rp * ir2 - rp), fxx = a.kxx[n] * rp * ir;
-          const double al_r = fvv * c0[0] + fwv * c1[0], al_i = fvv * c0[1] + fwv * c1[1];
-          const double be_r = fww * c1[0], be_i = fww * c1[1];
-          const double ga_r = fxx * c2[0], ga_i = fxx * c2[1];
-          const double yr = -(n + 1.0) * al_r + n * be_r, yi = -(n + 1.0) * al_i + n * be_i;
-          const double gr = al_r + be_r, gi = al_i + be_i;
-          const double D = rc[2] * q1 - rc[3] * qm1;   // dPbar/dtheta
-          const double Pb = st * q0;
-          const double mQ = m * q0;
-          srr += yr * Pb;
-          sri += yi * Pb;
-          // theta: G dPbar - i mQ X ; phi: i mQ G + dPbar X
-          str += gr * D + mQ * ga_i;
-          sti += gi * D - mQ * ga_r;
-          spr += -mQ * gi + D * ga_r;
-          spi += mQ * gr + D * ga_i;
-          const double q2 = rc[0] * (ct * q1 - rc[1] * q0);
-          qm1 = q0;
-          q0 = q1;
-          q1 = q2;
-          rp *= ir;
-        }
-      }
-      const double fac = (m == 0) ? 1.0 : 2.0;
-      ur += fac * (srr * cm - sri * sm_);
-      ut += fac * (str * cm - sti * sm_);
-      up += fac * (spr * cm - spi * sm_);
-    }
-    // spherical (about c_s) -> Cartesian
-    const double erx = st * cph, ery = st * sph, erz = ct;
-    const double etx = ct * cph, ety = ct * sph, etz = -st;
-    const double epx = -sph, epy = cph;
-    acc0 += ur * erx + ut * etx + up * epx;
-    acc1 += ur * ery + ut * ety + up * epy;
-    acc2 += ur * erz + ut * etz;
+    exterior_series(a, cs, rec, dx, dy, dz, acc0, acc1, acc2);
   }
   if (active) {
     double* uo = a.u + 3 * ((int64_t)t * a.P + g);
     uo[0] += acc0;
     uo[1] += acc1;
     uo[2] += acc2;
+  }
+}
+
+// Radial constants of the exterior series (Eqs. 3.6-3.11, exterior branches) of
+// a_S S + a_D D for n = 0..p.
+void series_radial(double a_s, double a_d, int p, double* kvv, double* kww, double* kwv, double* kxx) {
+  for (int n = 0; n <= p; ++n) {
+    const double dn = n;
+    kvv[n] = a_s * dn / ((2 * dn + 1) * (2 * dn + 3)) + a_d * (2 * dn * dn + 4 * dn + 3) / ((2 * dn + 1) * (2 * dn + 3));
+    if (n == 0) {
+      kww[n] = kwv[n] = kxx[n] = 0.0;
+      continue;
+    }
+    kww[n] = a_s * (dn + 1) / ((2 * dn + 1) * (2 * dn - 1)) + a_d * 2.0 * (dn + 1) * (dn - 1) / ((2 * dn + 1) * (2 * dn - 1));
+    kwv[n] = a_s * dn / (4 * dn + 2) + a_d * 2.0 * dn * (dn - 1) / (4 * dn + 2);
+    kxx[n] = a_s / (2 * dn + 1) + a_d * (dn - 1) / (2 * dn + 1);
   }
 }
 
@@ -181,20 +91,7 @@ void launch_near(bie_ctx* c, const OpSpec& spec, double* u) {
   a.mmax = c->mmax;
   a.P = c->P;
   a.ncoef = c->ncoef;
-  for (int n = 0; n <= c->p; ++n) {
-    const double dn = n;
-    // Eqs. 3.6-3.11, exterior branches, as a_S S + a_D D
-    a.kvv[n] = spec.a_s * dn / ((2 * dn + 1) * (2 * dn + 3)) +
-               spec.a_d * (2 * dn * dn + 4 * dn + 3) / ((2 * dn + 1) * (2 * dn + 3));
-    if (n == 0) {
-      a.kww[n] = a.kwv[n] = a.kxx[n] = 0.0;
-      continue;
-    }
-    a.kww[n] = spec.a_s * (dn + 1) / ((2 * dn + 1) * (2 * dn - 1)) +
-               spec.a_d * 2.0 * (dn + 1) * (dn - 1) / ((2 * dn + 1) * (2 * dn - 1));
-    a.kwv[n] = spec.a_s * dn / (4 * dn + 2) + spec.a_d * 2.0 * dn * (dn - 1) / (4 * dn + 2);
-    a.kxx[n] = spec.a_s / (2 * dn + 1) + spec.a_d * (dn - 1) / (2 * dn + 1);
-  }
+  series_radial(spec.a_s, spec.a_d, c->p, a.kvv, a.kww, a.kwv, a.kxx);
   const int threads = std::min(1024, ((c->P + 63) / 64) * 64);
   const size_t sm = 12 * (size_t)c->ncoef * sizeof(double);
   near_kernel<<<dim3((unsigned)c->nb), dim3(threads), sm, c->stream>>>(a);
