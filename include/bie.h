@@ -72,6 +72,13 @@ typedef struct {
   double near_gap;   /* surface-gap threshold d* of Eq. 4.5; <= 0 selects 1.0            */
   int device;        /* HIP device ordinal                                               */
   void* hip_stream;  /* hipStream_t for all device work (NULL = default stream)          */
+  int near_method;   /* near-pair evaluation: 0 = exterior series at the target nodes
+                        (Section 4.1), 1 = pole rotation with delayed evaluation
+                        (Section 4.2, Fig. 2): the source expansion is rotated so that
+                        its pole points at the target, evaluated on the translated
+                        target grid, projected, rotated back and summed per target
+                        before one inverse transform - the band-limited projection of
+                        the near field instead of its nodal values                       */
 } bie_opts;
 
 /* Builds the discretisation for n_spheres unit spheres (Eq. 4.2 grid, Legendre and

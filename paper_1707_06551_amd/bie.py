@@ -41,7 +41,7 @@ class MlpData(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int), ("n_phi", ctypes.c_int), ("near_gap", ctypes.c_double),
-                ("device", ctypes.c_int), ("hip_stream", ctypes.c_void_p)]
+                ("device", ctypes.c_int), ("hip_stream", ctypes.c_void_p), ("near_method", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -201,7 +201,7 @@ def _dptr(t):
 class Spheres:
     """A context for n_b unit spheres (bie_build_spheres)."""
 
-    def __init__(self, centres, p, n_phi=0, near_gap=1.0, device=0, stream=None):
+    def __init__(self, centres, p, n_phi=0, near_gap=1.0, device=0, stream=None, near_method=0):
         import torch
         L = lib()
         c = np.ascontiguousarray(centres, dtype=np.float64).reshape(-1, 3)
@@ -209,7 +209,7 @@ class Spheres:
             stream = torch.cuda.current_stream(device)
         self.stream = stream
         self.device = device
-        o = Opts(p, n_phi, near_gap, device, ctypes.c_void_p(stream.cuda_stream))
+        o = Opts(p, n_phi, near_gap, device, ctypes.c_void_p(stream.cuda_stream), near_method)
         h = ctypes.c_void_p()
         _check(L.bie_build_spheres(_hptr(c), c.shape[0], ctypes.byref(o), ctypes.byref(h)))
         self._h = h

@@ -106,6 +106,12 @@ struct bie_ctx {
   bie::DevBuf rg_partial;           // source splits x 6 nb double: mobility product partials
   bie::DevBuf rg_dots, rg_hist;     // block partial sums; CG scalars per iteration
   int rg_last_iters = 0;            // CG iterations of the last coarse solve
+
+  // near evaluation by pole rotation (near_rot.hip), near_method = 1
+  int near_method = 0;
+  bie::DevBuf wig;                  // sum_n (2n+1)^2 complex: Wigner matrices of R_x(-pi/2)
+  bie::DevBuf nearcoef;             // nb x 3 x ncoef x 2: summed near-field coefficients
+  bie::DevBuf tlat_d;               // nlat cos(theta_j)
 };
 
 namespace bie {
@@ -121,11 +127,13 @@ struct VshCall {
   bool coef_is_input = false;
   bool bordered = false;            // mobility matvec rows
   bool pc_border = false;           // mobility block preconditioner rows
+  bool accumulate = false;          // add the synthesis to u instead of overwriting it
   double c_identity = 0.0, scale_out = 1.0, wv1 = 0.0;
   double lam[3][33] = {};
 };
 void launch_vsh(bie_ctx* c, int precision, const VshCall& v);
 void launch_near(bie_ctx* c, const OpSpec& spec, double* u);
+void launch_near_rot(bie_ctx* c, const OpSpec& spec, double* u);
 void series_radial(double a_s, double a_d, int p, double* kvv, double* kww, double* kwv, double* kxx);
 void launch_far(bie_ctx* c, int precision, const OpSpec& spec, double* u);
 void apply(bie_ctx* c, int op, int precision, const double* mu, double* u);

@@ -79,6 +79,10 @@ void series_radial(double a_s, double a_d, int p, double* kvv, double* kww, doub
 
 void launch_near(bie_ctx* c, const OpSpec& spec, double* u) {
   if (c->near_idx.empty()) return;
+  if (c->near_method == 1) {
+    launch_near_rot(c, spec, u);
+    return;
+  }
   NearParams a{};
   a.coef = c->coef.as<double>();
   a.centres4 = c->centres4.as<double>();

@@ -132,6 +132,55 @@ void legendre_tables(int p, int mmax, double t, double s, const std::vector<int>
   }
 }
 
+// Matrices E_n = D^n(R_x(-pi/2)), n = 0..p, of the rotation of spherical harmonic
+// expansions (Y_n^m(T^T x) = sum_m' E_n[m', m] Y_n^m'(x), T = R_x(-pi/2), so
+// T^T x = (x, -z, y)), computed by their definition: the projection
+// E_n[m', m] = sum_g w_g conj(Y_n^m'(x_g)) Y_n^m(T^T x_g) on a Gauss-Legendre x uniform
+// grid of n + 1 latitudes and 2n + 2 longitudes, exact for products of degree-n
+// harmonics.  Layout: for each n, (2n+1) x (2n+1) complex, row m' + n, column m + n.
+static std::vector<double> wigner_x90(int p) {
+  std::vector<double> out;
+  std::vector<double> pm, qm, gt, gw;
+  for (int n = 0; n <= p; ++n) {
+    const int w = 2 * n + 1, nphi = 2 * n + 2;
+    gauss_legendre(n + 1, gt, gw);
+    std::vector<double> E(2 * (size_t)w * w, 0.0);
+    std::vector<double> ya(2 * w), yb(2 * w);
+    // Y_n^m at (t, phi), m = -n..n, no Condon-Shortley phase: Pbar_n^|m|(t) e^{i m phi}
+    auto ylm = [&](double t, double s, double phi, std::vector<double>& y) {
+      for (int m = 0; m <= n; ++m) {
+        legendre_column(m, n, t, s, pm, qm);
+        const double v = pm[n];
+        y[2 * (n + m)] = v * std::cos(m * phi);
+        y[2 * (n + m) + 1] = v * std::sin(m * phi);
+        y[2 * (n - m)] = v * std::cos(m * phi);
+        y[2 * (n - m) + 1] = -v * std::sin(m * phi);
+      }
+    };
+    for (int j = 0; j <= n; ++j) {
+      const double t = gt[j], s = std::sqrt(std::max(0.0, 1.0 - t * t));
+      for (int l = 0; l < nphi; ++l) {
+        const double phi = 2.0 * M_PI * l / nphi;
+        const double wt = 2.0 * M_PI * gw[j] / nphi;
+        const double x = s * std::cos(phi), y = s * std::sin(phi), z = t;
+        const double rx = x, ry = -z, rz = y;   // T^T x
+        const double rs = std::sqrt(std::max(0.0, rx * rx + ry * ry));
+        ylm(t, s, phi, ya);
+        ylm(rz, rs, std::atan2(ry, rx), yb);
+        for (int a = 0; a < w; ++a)
+          for (int b = 0; b < w; ++b) {
+            // conj(ya[a]) * yb[b]
+            const double ar = ya[2 * a], ai = -ya[2 * a + 1], br = yb[2 * b], bi = yb[2 * b + 1];
+            E[2 * (a * w + b)] += wt * (ar * br - ai * bi);
+            E[2 * (a * w + b) + 1] += wt * (ar * bi + ai * br);
+          }
+      }
+    }
+    out.insert(out.end(), E.begin(), E.end());
+  }
+  return out;
+}
+
 static void upload(DevBuf& b, const void* src, size_t bytes) {
   b.alloc(bytes);
   BIE_HIP(hipMemcpy(b.ptr, src, bytes, hipMemcpyHostToDevice));
@@ -156,6 +205,8 @@ void build(bie_ctx* c, const double* centres, int64_t nb, const bie_opts* o) {
   c->nb = nb;
   c->N = nb * c->P;
   c->near_gap = o->near_gap > 0 ? o->near_gap : 1.0;
+  if (o->near_method != 0 && o->near_method != 1) throw Error{BIE_EINVAL, "near_method must be 0 or 1"};
+  c->near_method = o->near_method;
   c->device = o->device;
   c->stream = (hipStream_t)o->hip_stream;
   BIE_HIP(hipSetDevice(c->device));
@@ -342,6 +393,11 @@ void build(bie_ctx* c, const double* centres, int64_t nb, const bie_opts* o) {
   int ns = (int)std::max<int64_t>(1, std::min<int64_t>((6144 + tblocks - 1) / tblocks, nb / 2));
   c->nsplit = std::max(1, std::min(ns, 64));
   c->partial.alloc((size_t)c->nsplit * c->N * 3 * sizeof(double));
+  upload_vec(c->tlat_d, tt);
+  if (c->near_method == 1) {
+    upload_vec(c->wig, wigner_x90(c->p));
+    c->nearcoef.alloc((size_t)nb * 3 * nc * 2 * sizeof(double));
+  }
   build_coarse(c);
   BIE_HIP(hipDeviceSynchronize());
 }

@@ -31,6 +31,7 @@ struct VshParams {
   double c_identity, scale_out;
   int do_self, bordered, coef_is_input, want_moments, write_q, q_float;
   int pc_border;   // isolated-sphere inverse of the bordered mobility block (preconditioner)
+  int accumulate;  // u += synthesis (else u = synthesis)
   double wv1;      // n = 1 coupling: V'_1 += wv1 * W_1 (preconditioner of the completed form)
   double lam[3][33];
 };
@@ -305,7 +306,7 @@ __global__ __launch_bounds__(256) void vsh_kernel(VshParams a) {
       out[1] += 1.5 * pv[1] + 3.0 * (pw[2] * fr[0] - pw[0] * fr[2]);
       out[2] += 1.5 * pv[2] + 3.0 * (pw[0] * fr[1] - pw[1] * fr[0]);
     }
-    for (int d = 0; d < 3; ++d) a.u[3 * (base + g) + d] = out[d];
+    for (int d = 0; d < 3; ++d) a.u[3 * (base + g) + d] = a.accumulate ? a.u[3 * (base + g) + d] + out[d] : out[d];
   }
   if (a.pc_border && tid < 6) {
     if (tid < 3)
@@ -361,6 +362,7 @@ void launch_vsh(bie_ctx* c, int precision, const VshCall& v) {
   a.write_q = v.write_q ? 1 : 0;
   a.q_float = f32 ? 1 : 0;
   a.pc_border = v.pc_border ? 1 : 0;
+  a.accumulate = v.accumulate ? 1 : 0;
   a.wv1 = v.wv1;
   for (int f = 0; f < 3; ++f)
     for (int n = 0; n < 33; ++n) a.lam[f][n] = v.lam[f][n];
