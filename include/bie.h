@@ -202,6 +202,29 @@ int bie_apply_precond(bie_ctx* ctx, int op, int precision, int precond, const do
  * after writing the others.  n_targets = 0 is a no-op.  Synchronises the stream. */
 int bie_eval_field(bie_ctx* ctx, int op, const double* mu, int64_t n_targets, const double* targets, double* u);
 
+/* ---- Laplace single layer and the magnetostatic problem (Problem 3) ---------------
+ * S^L[q](x) = int q / (4 pi |x - y|) over all spheres, evaluated as the Stokes operators
+ * are: the own sphere spectrally (Theorem 1: S^L[Y_n^m] = Y_n^m / (2n+1), normal
+ * derivative K^L with principal value -1 / (2(2n+1)), both on the band-limited
+ * projection), near spheres by Eq. 3.3 and its gradient, others by the smooth
+ * quadrature of Eq. 4.4.  Float64.
+ * kind 0: out (device, N) = (1/2 I + eta K^L)[q], the operator of Eq. 5.13;
+ * kind 1: out (device, N x 3) = gradient of S^L[q] at every node, exterior side (eta
+ *         unused).  q: device float64, N scalar node values. */
+int bie_apply_laplace(bie_ctx* ctx, int kind, double eta, const double* q, double* out);
+
+/* Problem 3 (Eqs. 5.9-5.13): paramagnetic spheres in the imposed field H0 (host, 3),
+ * eta = (mu - mu0) / (mu + mu0) in (-1, 1).  Solves (1/2 I + eta K^L)[q] = eta H0 . n
+ * with the library's GMRES (float64; opts->precision is ignored, BIE_PC_M0 selects the
+ * isolated-sphere inverse, BIE_PC_RIGID / BIE_PC_MLP are ignored), then evaluates
+ * H = H0 - grad S^L[q] on the fluid side of every node and the Maxwell traction
+ * t = (H . n) H - |H|^2 n / 2 (mu0 = 1), and returns each sphere's force F = int t and
+ * torque T = int (x - c) x t (host, n_b x 3).  The flow couples to the field only
+ * through these loads (Section 5): bie_solve_mobility(F, T) gives the particle
+ * velocities.  q: optional device output (N), else NULL.  Synchronises the stream. */
+int bie_solve_magnetic(bie_ctx* ctx, const double* H0, double eta, const bie_solve_opts* opts, double* q, double* F,
+                       double* T, bie_solve_info* info);
+
 /* ---- learned close-pair coarse correction (no counterpart in the paper) -------------
  * Coarse space per sphere: the vector spherical harmonics of degree <= 2 (Definition
  * 2.2) in a Cartesian parametrisation of 25 coefficients (s; a; b; c; tV; tW; tX):

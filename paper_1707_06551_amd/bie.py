@@ -25,6 +25,7 @@ EXPORTED = [
     "bie_vsh_forward", "bie_vsh_inverse", "bie_solve_resistance", "bie_solve_mobility", "bie_last_error",
     "bie_solve", "bie_apply_precond", "bie_lowmodes", "bie_lowmodes_synth", "bie_pair_geometry",
     "bie_mlp_n_weights", "bie_precond_load", "bie_mlp_eval", "bie_mlp_train", "bie_eval_field",
+    "bie_apply_laplace", "bie_solve_magnetic",
 ]
 NLOW = 25
 NFEAT = 8
@@ -98,6 +99,10 @@ def lib():
     L.bie_apply_precond.restype = I
     L.bie_eval_field.argtypes = [VP, I, VP, I64, VP, VP]
     L.bie_eval_field.restype = I
+    L.bie_apply_laplace.argtypes = [VP, I, D, VP, VP]
+    L.bie_apply_laplace.restype = I
+    L.bie_solve_magnetic.argtypes = [VP, VP, D, P(SolveOpts), VP, VP, VP, P(SolveInfo)]
+    L.bie_solve_magnetic.restype = I
     L.bie_lowmodes.argtypes = [VP, VP, VP]
     L.bie_lowmodes.restype = I
     L.bie_lowmodes_synth.argtypes = [VP, VP, VP]
@@ -279,6 +284,28 @@ class Spheres:
         z = torch.empty_like(r)
         _check(lib().bie_apply_precond(self._h, op, precision, precond, _dptr(r), _dptr(z)))
         return z
+
+    def apply_laplace(self, kind, q, eta=0.0, out=None):
+        """kind 0: (1/2 I + eta K^L)[q] (N); kind 1: exterior gradient of S^L[q] (3N)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.N * (1 if kind == 0 else 3), dtype=torch.float64, device=q.device)
+        _check(lib().bie_apply_laplace(self._h, kind, eta, _dptr(q), _dptr(out)))
+        return out
+
+    def solve_magnetic(self, H0, eta, tol=1e-10, restart=100, max_iter=1000, precond=PC_M0, want_q=False):
+        """Problem 3: magnetic forces and torques (nb, 3) on the spheres in the field H0."""
+        import torch
+        h = np.ascontiguousarray(H0, dtype=np.float64).reshape(3)
+        F = np.empty((self.nb, 3))
+        T = np.empty((self.nb, 3))
+        q = torch.empty(self.N, dtype=torch.float64, device=f"cuda:{self.device}") if want_q else None
+        info = SolveInfo()
+        so = self._sopts(tol, restart, max_iter, FP64, precond, 1e-4)
+        rc = lib().bie_solve_magnetic(self._h, _hptr(h), eta, ctypes.byref(so), _dptr(q) if q is not None else None,
+                                      _hptr(F), _hptr(T), ctypes.byref(info))
+        _check(rc, allow_noconv=True)
+        return F, T, q, dict(info.as_dict(), converged=(rc == OK))
 
     def eval_field(self, op, mu, targets, u=None):
         """Layer potential of op (OP_S, OP_D, OP_SD_BIE, OP_DN_BIE) of the node density mu

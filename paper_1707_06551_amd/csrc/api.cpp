@@ -2,13 +2,13 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "bie_internal.h"
 
 namespace bie {
 void build(bie_ctx* c, const double* centres, int64_t nb, const bie_opts* o);
 const char* last_error();
-int solve(bie_ctx* c, int op, const double* b, double* x, int64_t n, const bie_solve_opts* so, bie_solve_info* info);
 
 // Table 3.12: S, D_+ eigenvalues per family (V, W, X) and degree n.
 static void eig_S(int n, double e[3]) {
@@ -38,6 +38,10 @@ static void self_lambda(const OpSpec& s, int p, double lam[3][33]) {
 }
 
 void apply(bie_ctx* c, int op, int precision, const double* mu, double* u) {
+  if (op == OP_LAPLACE) {
+    lap_apply(c, mu, u);
+    return;
+  }
   const int base = op & 0xff;
   int stages = op & (BIE_STAGE_SELF | BIE_STAGE_NEAR | BIE_STAGE_FAR);
   if (stages == 0) stages = BIE_STAGE_SELF | BIE_STAGE_NEAR | BIE_STAGE_FAR;
@@ -99,6 +103,13 @@ void dev_precond_m0(bie_ctx* c, int op_base, int precision, const double* r, dou
 }
 
 void apply_precond(bie_ctx* c, int op_base, int precision, int precond, const double* r, double* z) {
+  if (op_base == OP_LAPLACE) {
+    if (precond == BIE_PC_NONE)
+      dev_copy(c, r, z, c->N);
+    else
+      lap_precond(c, r, z);
+    return;
+  }
   if (op_base != BIE_OP_DN_BIE && op_base != BIE_OP_MOBILITY && op_base != BIE_OP_SD_BIE)
     throw Error{BIE_EINVAL, "preconditioners exist for BIE_OP_DN_BIE, BIE_OP_MOBILITY and BIE_OP_SD_BIE"};
   if (precision != BIE_FP64 && precision != BIE_MIXED) throw Error{BIE_EINVAL, "bad precision"};
@@ -366,6 +377,45 @@ int bie_apply_precond(bie_ctx* c, int op, int precision, int precond, const doub
   }
   BIE_TRY(bie::apply_precond(c, op, precision, precond, r, z));
   return BIE_OK;
+}
+
+int bie_apply_laplace(bie_ctx* c, int kind, double eta, const double* q, double* out) {
+  if (!c || !q || !out || q == out || (kind != 0 && kind != 1)) {
+    bie::set_error("bie_apply_laplace: bad arguments");
+    return BIE_EINVAL;
+  }
+  BIE_TRY(if (kind == 0) {
+    c->lap_eta = eta;
+    bie::lap_apply(c, q, out);
+  } else {
+    bie::lap_grad(c, q, out);
+  });
+  return BIE_OK;
+}
+
+int bie_solve_magnetic(bie_ctx* c, const double* H0, double eta, const bie_solve_opts* opts, double* q, double* F,
+                       double* T, bie_solve_info* info) {
+  if (!c || !H0 || !F || !T) {
+    bie::set_error("bie_solve_magnetic: null argument");
+    return BIE_EINVAL;
+  }
+  int rc = BIE_OK;
+  BIE_TRY({
+    bie::DevBuf qtmp;
+    double* qd = q;
+    if (!qd) {
+      qtmp.alloc(c->N * sizeof(double));
+      qd = qtmp.as<double>();
+    }
+    std::vector<double> ft(6 * c->nb);
+    bie::solve_magnetic(c, H0, eta, opts, qd, ft.data(), info, &rc);
+    for (int64_t k = 0; k < c->nb; ++k)
+      for (int d = 0; d < 3; ++d) {
+        F[3 * k + d] = ft[6 * k + d];
+        T[3 * k + d] = ft[6 * k + 3 + d];
+      }
+  });
+  return rc;
 }
 
 int bie_eval_field(bie_ctx* c, int op, const double* mu, int64_t n_targets, const double* targets, double* u) {

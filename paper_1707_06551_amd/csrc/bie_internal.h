@@ -112,6 +112,10 @@ struct bie_ctx {
   bie::DevBuf wig;                  // sum_n (2n+1)^2 complex: Wigner matrices of R_x(-pi/2)
   bie::DevBuf nearcoef;             // nb x 3 x ncoef x 2: summed near-field coefficients
   bie::DevBuf tlat_d;               // nlat cos(theta_j)
+
+  // Laplace single layer and the magnetostatic problem (laplace.hip)
+  bie::DevBuf lapcoef;              // nb x ncoef x 2 scalar coefficients
+  double lap_eta = 0.0;             // eta of Eq. 5.13 for the current solve
 };
 
 namespace bie {
@@ -158,6 +162,16 @@ void coarse_correct(bie_ctx* c, const double* r, double* z);
 // global rigid-mode coarse correction: z <- z + P (A_c^-1 R r - R z)
 constexpr int64_t RIGID_MAX_SPHERES = 65536;
 void rigid_correct(bie_ctx* c, const double* r, double* z);
+
+// Laplace / magnetostatic operators (laplace.hip); OP_LAPLACE is the solver's internal
+// operator code for (1/2 I + eta K^L) on N scalar unknowns
+constexpr int OP_LAPLACE = 0x40;
+void lap_apply(bie_ctx* c, const double* q, double* out);
+void lap_precond(bie_ctx* c, const double* r, double* z);
+void lap_grad(bie_ctx* c, const double* q, double* grad);
+void solve_magnetic(bie_ctx* c, const double H0[3], double eta, const bie_solve_opts* opts, double* q_dev,
+                    double* ft_host, bie_solve_info* info, int* rc);
+int solve(bie_ctx* c, int op, const double* b, double* x, int64_t n, const bie_solve_opts* so, bie_solve_info* info);
 
 // layer potentials at fluid points (field.hip)
 void eval_field(bie_ctx* c, int op_base, const double* mu, int64_t M, const double* x, double* u);
