@@ -86,3 +86,18 @@ def test_solve_stays_within_the_projection_error():
     print(f"rotation vs direct near evaluation, 8 spheres p = 8: |dF|/|F| {eF:.2e}, |dT|/|T| {eT:.2e}")
     assert eF < 1e-3 and eT < 1e-3
     s.close()
+
+
+def test_near_stage_with_wider_azimuthal_grid():
+    # n_phi = 2p + 2 (mmax = p): orders up to p are kept on the target grid
+    from paper_1707_06551_amd import bie
+    c = small_cluster(7, 7.5, 0.3, 5)
+    p = 6
+    s = bie.Spheres(c, p, n_phi=2 * p + 2, near_gap=1.0, near_method=1)
+    g = Geometry(c, p, n_phi=2 * p + 2, near_gap=1.0)
+    assert g.near.sum() > 0 and g.mmax == p
+    mu = np.random.default_rng(9).standard_normal((g.N, 3))
+    out = host(s.apply(OPS["SD_BIE"] | bie.STAGE_NEAR, dev(mu))).reshape(g.N, 3)
+    ref = rn.near_part(g, mu, 1.0, 1.0)
+    assert rel_err(out, ref) < 1e-11, (rel_err(out, ref), max_rel(out, ref))
+    s.close()
