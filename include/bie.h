@@ -238,7 +238,9 @@ int bie_solve_magnetic(bie_ctx* ctx, const double* H0, double eta, const bie_sol
  * directed near pair by an MLP (8 -> 64 -> 64 -> 278, tanh, float32) of the pair's
  * features: gap g, log(g + 0.01), 0.1/(g + 0.1), near counts of i and j / 8, smallest
  * other gap of i and of j (near_gap if none), sum_{k near i} 0.1/(g_ik + 0.1).
- * The correction acts on the resistance form; for mobility BIE_PC_MLP is M0. */
+ * The correction acts on the density part of the resistance and mobility forms (the
+ * network is trained per form: weights/precond_dn*.npz, weights/precond_mob.npz); for
+ * BIE_OP_SD_BIE BIE_PC_MLP is M0. */
 
 /* rho = R f: f device 3N float64 -> rho device n_b x 25 float64. */
 int bie_lowmodes(bie_ctx* ctx, const double* f, double* rho);

@@ -132,12 +132,13 @@ void apply_precond(bie_ctx* c, int op_base, int precision, int precond, const do
     default:
       throw Error{BIE_EINVAL, "unknown preconditioner"};
   }
-  // Both corrections act on the resistance form only (the mobility form carries the
-  // rigid motions as unknowns with their own rows).  The global rigid-mode correction
-  // resets the rigid part of M0 r; the learned close-pair correction is added after it,
-  // so that a network trained on that base keeps its rigid-mode output.
-  if (op_base != BIE_OP_DN_BIE) return;
-  if (rigid) rigid_correct(c, r, z);
+  // The global rigid-mode correction acts on the resistance form only (the mobility form
+  // carries the rigid motions as unknowns with their own rows); it resets the rigid part
+  // of M0 r.  The learned close-pair correction acts on the density part of the
+  // resistance and mobility forms (weights are trained per form) and is added last, so
+  // that a network trained on a base keeps its rigid-mode output.
+  if (op_base == BIE_OP_SD_BIE) return;
+  if (rigid && op_base == BIE_OP_DN_BIE) rigid_correct(c, r, z);
   if (base == BIE_PC_MLP) coarse_correct(c, r, z);
 }
 

@@ -22,6 +22,7 @@ WORKLOADS = {
     "spheres1024_p16": dict(n=1024, p=16, phi=0.30, min_gap=0.02, problem="resistance", tol=1e-8),
     "spheres2048_p12_slip": dict(n=2048, p=12, phi=0.25, min_gap=0.02, problem="mobility_slip", tol=1e-8),
     "spheres64_p16_train": dict(n=64, p=16, phi=0.25, min_gap=0.02, problem="resistance", tol=1e-10),
+    "spheres64_p12_slip_train": dict(n=64, p=12, phi=0.25, min_gap=0.02, problem="mobility_slip", tol=1e-10),
 }
 
 

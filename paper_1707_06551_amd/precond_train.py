@@ -1,17 +1,22 @@
 """Training driver of the learned close-pair coarse correction (BIE_PC_MLP).
 
-Data: for each training configuration (seeded placements of the 64-sphere training
+Data: for each training configuration (seeded placements of a 64-sphere training
 workload), random low-mode right-hand sides b = P xi (xi ~ N(0, 1), 25 coefficients per
-sphere) are solved with the plain float64 method (A x = b, completed double-layer
-form); the target is t = R x - R B b, the part of the low-mode response that the base
-preconditioner B misses: the isolated-sphere inverse M0 (--base m0), or M0 followed by
-the global rigid-mode coarse correction (--base m0r, BIE_PC_RIGID).  Training runs on
+sphere) are solved with the plain float64 method; the target is t = R x - R B b, the
+part of the low-mode response that the base preconditioner B misses.  Two forms:
+  --form dn   the completed double-layer (resistance) form, A x = b; B is the
+              isolated-sphere inverse M0 (--base m0), or M0 followed by the global
+              rigid-mode coarse correction (--base m0r, BIE_PC_RIGID);
+  --form mob  the bordered mobility form (Eqs. 5.15, 5.17) with b = [P xi; 0], a
+              low-mode slip with no applied force or torque; B = M0 and R, P act on
+              the density part only.  Training runs on
 the GPU in the library's own forward / backward / Adam kernels (bie_mlp_train).
 Applied at full strength the additive correction over-corrects, so a relaxation omega
 (theta -> omega theta) is chosen on held-out configurations by GMRES iteration count
 and folded into the saved output layer.
 
 Usage: python -m paper_1707_06551_amd.precond_train --configs 200 --rhs 4 --p 16 --epochs 400 [--base m0r]
+       python -m paper_1707_06551_amd.precond_train --form mob --configs 200 --rhs 4 --p 12 --epochs 400
 """
 import argparse
 import json
@@ -21,7 +26,7 @@ import time
 import numpy as np
 
 from . import bie
-from .inputs import make_workload
+from .inputs import make_workload, slip_field
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_WEIGHTS = os.path.join(HERE, "weights", "precond_dn.npz")
@@ -45,37 +50,44 @@ def init_weights(seed=0, out_scale=1e-3):
 
 
 BASES = {"m0": bie.PC_M0, "m0r": bie.PC_M0 | bie.PC_RIGID}
-DEFAULT_FILES = {"m0": DEFAULT_WEIGHTS, "m0r": os.path.join(HERE, "weights", "precond_dn_rigid.npz")}
+DEFAULT_FILES = {"m0": DEFAULT_WEIGHTS, "m0r": os.path.join(HERE, "weights", "precond_dn_rigid.npz"),
+                 "mob": os.path.join(HERE, "weights", "precond_mob.npz")}
+# per form: operator, training workload
+FORMS = {"dn": (bie.OP_DN_BIE, "spheres64_p16_train"), "mob": (bie.OP_MOBILITY, "spheres64_p12_slip_train")}
 
 
-def config_samples(sph, n_rhs, rng, tol=1e-8, base=bie.PC_M0):
+def config_samples(sph, n_rhs, rng, tol=1e-8, base=bie.PC_M0, op=bie.OP_DN_BIE):
     """(xi, target) of one configuration: (nb, n_rhs, 25) each, plus solve statistics."""
     import torch
     xi = rng.standard_normal((sph.nb, n_rhs, bie.NLOW))
     target = np.empty_like(xi)
     iters = []
+    n3 = 3 * sph.N
     for r in range(n_rhs):
         rho = torch.from_numpy(np.ascontiguousarray(xi[:, r, :]).reshape(-1)).cuda()
         b = sph.lowmodes_synth(rho)
-        x, info = sph.solve(bie.OP_DN_BIE, b, tol=tol, precision=bie.FP64, precond=base)
+        if op == bie.OP_MOBILITY:
+            b = torch.cat([b, torch.zeros(6 * sph.nb, dtype=b.dtype, device=b.device)])
+        x, info = sph.solve(op, b, tol=tol, precision=bie.FP64, precond=base)
         if not info["converged"]:
             raise RuntimeError(f"training solve did not converge: {info}")
         iters.append(info["iters"])
-        z0 = sph.apply_precond(bie.OP_DN_BIE, b, precond=base)
-        t = sph.lowmodes(x) - sph.lowmodes(z0)
+        z0 = sph.apply_precond(op, b, precond=base)
+        t = sph.lowmodes(x[:n3].contiguous()) - sph.lowmodes(z0[:n3].contiguous())
         torch.cuda.synchronize()
         target[:, r, :] = t.cpu().numpy().reshape(sph.nb, bie.NLOW)
     return xi, target, iters
 
 
-def build_set(n_configs, n_rhs, p, seed0=1000, workload="spheres64_p16_train", log=print, base=bie.PC_M0):
+def build_set(n_configs, n_rhs, p, seed0=1000, workload="spheres64_p16_train", log=print, base=bie.PC_M0,
+              op=bie.OP_DN_BIE):
     ts = bie.TrainingSet(n_rhs)
     t0 = time.time()
     for k in range(n_configs):
         w = make_workload(workload, seed=seed0 + k)
         sph = bie.Spheres(w["centres"], p, near_gap=1.0)
         pi, pj, feats, frames = sph.pair_geometry()
-        xi, target, iters = config_samples(sph, n_rhs, np.random.default_rng(seed0 + k + 7919), base=base)
+        xi, target, iters = config_samples(sph, n_rhs, np.random.default_rng(seed0 + k + 7919), base=base, op=op)
         ts.add(pi, pj, feats, frames, xi, target)
         sph.close()
         if log and (k % 20 == 0 or k == n_configs - 1):
@@ -97,17 +109,30 @@ def select_relaxation(w, p, seeds, omegas=(0.1, 0.15, 0.2, 0.25, 0.3, 0.4, 0.6, 
                       log=print, base=bie.PC_M0):
     """The additive correction over-corrects at full strength; choose the relaxation
     omega (theta -> omega theta) that minimises the float64 GMRES iterations of the
-    resistance problem on held-out configurations."""
+    workload's problem (resistance, or mobility with active slip) on held-out
+    configurations."""
+    import torch
     table = {om: [] for om in omegas}
     base_its = []
+
+    def run(sph, wk, slip, pc):
+        if wk["problem"] == "resistance":
+            return sph.solve_resistance(wk["v"], wk["omega"], tol=1e-8, precond=pc)[-1]["iters"]
+        return sph.solve_mobility(wk["F"], wk["T"], slip=slip, tol=1e-8, precond=pc)[-1]["iters"]
+
     for sd in seeds:
         wk = make_workload(workload, seed=sd)
         sph = bie.Spheres(wk["centres"], p, near_gap=1.0)
-        base_its.append(sph.solve_resistance(wk["v"], wk["omega"], tol=1e-8, precond=base)[-1]["iters"])
+        slip = None
+        if wk["problem"] == "mobility_slip":
+            xyz, _ = sph.nodes()
+            sphere_of = np.arange(sph.N) // sph.P
+            slip = torch.from_numpy(slip_field(wk["slip_coef"], xyz - wk["centres"][sphere_of], sphere_of)
+                                    .reshape(-1)).cuda()
+        base_its.append(run(sph, wk, slip, base))
         for om in omegas:
             sph.load_precond(scaled(w, om))
-            table[om].append(sph.solve_resistance(wk["v"], wk["omega"], tol=1e-8,
-                                                  precond=bie.PC_MLP | (base & bie.PC_RIGID))[-1]["iters"])
+            table[om].append(run(sph, wk, slip, bie.PC_MLP | (base & bie.PC_RIGID)))
         sph.close()
     best = min(omegas, key=lambda om: (sum(table[om]), om))
     if log:
@@ -137,13 +162,18 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--select", type=int, default=4, help="held-out configurations for choosing the relaxation")
     ap.add_argument("--base", choices=sorted(BASES), default="m0",
-                    help="preconditioner the correction is trained on top of (m0r: M0 + BIE_PC_RIGID)")
+                    help="preconditioner the correction is trained on top of (m0r: M0 + BIE_PC_RIGID, dn form only)")
+    ap.add_argument("--form", choices=sorted(FORMS), default="dn",
+                    help="dn: resistance (completed double-layer) form; mob: bordered mobility form with slip")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
+    if args.form == "mob" and args.base != "m0":
+        ap.error("the mobility form is trained on M0 only (BIE_PC_RIGID acts on the resistance form)")
     base = BASES[args.base]
-    out = args.out or DEFAULT_FILES[args.base]
-    train = build_set(args.configs, args.rhs, args.p, seed0=1000, base=base)
-    hold = build_set(args.holdout, args.rhs, args.p, seed0=900000, base=base)
+    op, workload = FORMS[args.form]
+    out = args.out or DEFAULT_FILES["mob" if args.form == "mob" else args.base]
+    train = build_set(args.configs, args.rhs, args.p, seed0=1000, base=base, op=op, workload=workload)
+    hold = build_set(args.holdout, args.rhs, args.p, seed0=900000, base=base, op=op, workload=workload)
     w0 = init_weights(0)
     l0, _ = hold.eval(w0)
     t0 = time.time()
@@ -151,8 +181,10 @@ def main():
     t_train = time.time() - t0
     l1, _ = hold.eval(w)
     ltr, _ = train.eval(w)
-    omega, table, base_its = select_relaxation(w, args.p, seeds=[600000 + k for k in range(args.select)], base=base)
-    meta = dict(version=1, formulation="DN_BIE", base=args.base, p=args.p, hidden=HIDDEN, nfeat=bie.NFEAT, nout=278,
+    omega, table, base_its = select_relaxation(w, args.p, seeds=[600000 + k for k in range(args.select)], base=base,
+                                               workload=workload)
+    meta = dict(version=1, formulation="MOBILITY" if args.form == "mob" else "DN_BIE", base=args.base,
+                workload=workload, p=args.p, hidden=HIDDEN, nfeat=bie.NFEAT, nout=278,
                 configs=args.configs, rhs=args.rhs, epochs=args.epochs, lr=args.lr, batch=args.batch,
                 train_loss=float(ltr), holdout_loss_init=float(l0), holdout_loss=float(l1),
                 train_seconds=t_train, relaxation=omega, relaxation_scan=table, base_iters=base_its,

@@ -63,7 +63,12 @@ def main():
     weights = None
     if args.precond in ("mlp", "mlpr"):
         from .precond_train import DEFAULT_FILES, load_weights
-        weights = load_weights(args.weights or DEFAULT_FILES["m0r" if args.precond == "mlpr" else "m0"])[0]
+        from .inputs import WORKLOADS
+        if args.precond == "mlpr":
+            key = "m0r"
+        else:
+            key = "m0" if WORKLOADS[args.workload]["problem"] == "resistance" else "mob"
+        weights = load_weights(args.weights or DEFAULT_FILES[key])[0]
     rows = []
     for k in range(args.seeds):
         w = make_workload(args.workload, seed=args.seed0 + k)
