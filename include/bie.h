@@ -55,6 +55,15 @@ extern "C" {
                              input [mu (3N); v (3 n_b); omega (3 n_b)], output
                              [1/2 mu + sum (S+D) mu - v_i - omega_i x (x - c_i);
                               (1/4pi) int_k mu;  (3/8pi) int_k (y - c_k) x mu]           */
+#define BIE_OP_K 6        /* sum_k K_k[sigma]: traction of the single layer at the target
+                             node with the target's normal (Eq. 2.22, kernel
+                             -3/(4 pi) r (r.sigma)(r.n_x)/|r|^5, r = x - y); on the own
+                             sphere the principal value K_pv = (K_+ + K_-)/2 of Table 3.12
+                             (equal to D_pv on every mode); near pairs by the traction of
+                             the exterior series (Eqs. 3.17-3.18) at the node            */
+#define BIE_OP_KL_BIE 7   /* 1/2 mu + sum_k (K_k + L_k)[mu], the operator of Eq. 5.8;
+                             L_k[mu] = int_k mu + (int_k (y - c_k) x mu) x (x - c_k) on the
+                             nodes of sphere k only                                      */
 /* Stage selectors, OR-ed into op (testing and profiling; default = all stages). */
 #define BIE_STAGE_SELF 0x100 /* identity + self term (+ bordered rows for MOBILITY)      */
 #define BIE_STAGE_NEAR 0x200 /* near-pair series                                         */
@@ -177,7 +186,20 @@ int bie_solve_resistance(bie_ctx* ctx, const double* v, const double* omega, con
 int bie_solve_mobility(bie_ctx* ctx, const double* F, const double* T, const double* slip,
                        const bie_solve_opts* opts, double* v, double* omega, double* mu, bie_solve_info* info);
 
-/* Generic solve of op (BIE_OP_DN_BIE, BIE_OP_MOBILITY or BIE_OP_SD_BIE) with a caller
+/* Mobility problem in the paper's own formulation (Problem 2, Eqs. 5.7-5.8): with the
+ * force density rho_k = F_k / (4 pi) + 3/(8 pi) T_k x (x - c_k) (int rho = F_k,
+ * int (x - c_k) x rho = T_k; F, T host n_b x 3, the force and torque each particle
+ * exerts on the fluid), solve (1/2 I + sum (K_k + L_k)) mu = -(1/2 I + sum K_k) rho, then
+ * u = sum S_k[mu + rho] on the surfaces gives v_k = (1/4 pi) int_k u and
+ * omega_k = 3/(8 pi) int_k (x - c_k) x u (host outputs, n_b x 3).  opts->precond:
+ * BIE_PC_NONE or BIE_PC_M0 (isolated-sphere inverse of 1/2 + K_pv + L); precision as in
+ * bie_solve (the right-hand side and the final single layer are float64).  mu: optional
+ * device output (3N), the solved density without rho.  near_method must be 0.
+ * Synchronises the stream.  info may be NULL. */
+int bie_solve_mobility_traction(bie_ctx* ctx, const double* F, const double* T, const bie_solve_opts* opts,
+                                double* v, double* omega, double* mu, bie_solve_info* info);
+
+/* Generic solve of op (BIE_OP_DN_BIE, BIE_OP_MOBILITY, BIE_OP_SD_BIE or BIE_OP_KL_BIE) with a caller
  * right-hand side: b, x device float64 of length 3N (3N + 6 n_b for mobility).  With
  * BIE_OP_SD_BIE and b = -u_inf at the nodes this is the porous-media problem (Problem 1,
  * Eq. 5.4: spheres held fixed in an imposed flow u_inf); the flow is then
@@ -186,8 +208,9 @@ int bie_solve_mobility(bie_ctx* ctx, const double* F, const double* T, const dou
 int bie_solve(bie_ctx* ctx, int op, const double* b, double* x, const bie_solve_opts* opts, bie_solve_info* info);
 
 /* z = M r for the preconditioner precond (BIE_PC_*) of op (BIE_OP_DN_BIE,
- * BIE_OP_MOBILITY or BIE_OP_SD_BIE; for BIE_OP_SD_BIE, M0 inverts 1/2 + S + D_pv of each
- * isolated sphere and the corrections do not apply), in the given precision.
+ * BIE_OP_MOBILITY, BIE_OP_SD_BIE or BIE_OP_KL_BIE; for BIE_OP_SD_BIE, M0 inverts
+ * 1/2 + S + D_pv of each isolated sphere and the corrections do not apply; for
+ * BIE_OP_KL_BIE only BIE_PC_NONE and BIE_PC_M0 exist), in the given precision.
  * r, z: device float64, length 3N (3N + 6 n_b for mobility), must not alias. */
 int bie_apply_precond(bie_ctx* ctx, int op, int precision, int precond, const double* r, double* z);
 

@@ -14,6 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbie.so")
 
 OP_S, OP_D, OP_SD_BIE, OP_DN_BIE, OP_MOBILITY = 1, 2, 3, 4, 5
+OP_K, OP_KL_BIE = 6, 7   # single-layer traction; 1/2 I + K + L of the traction mobility form
 STAGE_SELF, STAGE_NEAR, STAGE_FAR = 0x100, 0x200, 0x400
 FP64, MIXED = 0, 1
 PC_NONE, PC_M0, PC_MLP = 0, 1, 2
@@ -25,7 +26,7 @@ EXPORTED = [
     "bie_vsh_forward", "bie_vsh_inverse", "bie_solve_resistance", "bie_solve_mobility", "bie_last_error",
     "bie_solve", "bie_apply_precond", "bie_lowmodes", "bie_lowmodes_synth", "bie_pair_geometry",
     "bie_mlp_n_weights", "bie_precond_load", "bie_mlp_eval", "bie_mlp_train", "bie_eval_field",
-    "bie_apply_laplace", "bie_solve_magnetic",
+    "bie_apply_laplace", "bie_solve_magnetic", "bie_solve_mobility_traction",
 ]
 NLOW = 25
 NFEAT = 8
@@ -91,6 +92,8 @@ def lib():
     L.bie_solve_resistance.restype = I
     L.bie_solve_mobility.argtypes = [VP, VP, VP, VP, P(SolveOpts), VP, VP, VP, P(SolveInfo)]
     L.bie_solve_mobility.restype = I
+    L.bie_solve_mobility_traction.argtypes = [VP, VP, VP, P(SolveOpts), VP, VP, VP, P(SolveInfo)]
+    L.bie_solve_mobility_traction.restype = I
     L.bie_last_error.argtypes = []
     L.bie_last_error.restype = ctypes.c_char_p
     L.bie_solve.argtypes = [VP, I, VP, VP, P(SolveOpts), P(SolveInfo)]
@@ -270,7 +273,7 @@ class Spheres:
         return u
 
     def solve(self, op, b, tol=1e-8, restart=100, max_iter=1000, precision=FP64, precond=PC_NONE, inner_tol=1e-4):
-        """Generic solve A x = b (device tensors) for OP_DN_BIE or OP_MOBILITY."""
+        """Generic solve A x = b (device tensors) for OP_DN_BIE, OP_MOBILITY, OP_SD_BIE or OP_KL_BIE."""
         import torch
         x = torch.empty_like(b)
         info = SolveInfo()
@@ -367,6 +370,22 @@ class Spheres:
                                         _dptr(psi) if psi is not None else None, ctypes.byref(info))
         _check(rc, allow_noconv=True)
         return F, T, psi, dict(info.as_dict(), converged=(rc == OK))
+
+    def solve_mobility_traction(self, F, T, tol=1e-8, restart=100, max_iter=1000, precision=FP64,
+                                precond=PC_M0, inner_tol=1e-4, want_mu=False):
+        """Problem 2 in the paper's form (Eqs. 5.7-5.8): (v, omega, mu or None, info)."""
+        import torch
+        F = np.ascontiguousarray(F, dtype=np.float64)
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        v = np.empty((self.nb, 3))
+        om = np.empty((self.nb, 3))
+        mu = torch.empty(3 * self.N, dtype=torch.float64, device=f"cuda:{self.device}") if want_mu else None
+        info = SolveInfo()
+        so = self._sopts(tol, restart, max_iter, precision, precond, inner_tol)
+        rc = lib().bie_solve_mobility_traction(self._h, _hptr(F), _hptr(T), ctypes.byref(so), _hptr(v), _hptr(om),
+                                               _dptr(mu) if mu is not None else None, ctypes.byref(info))
+        _check(rc, allow_noconv=True)
+        return v, om, mu, dict(info.as_dict(), converged=(rc == OK))
 
     def solve_mobility(self, F, T, slip=None, tol=1e-8, restart=100, max_iter=1000, precision=FP64,
                        precond=PC_NONE, inner_tol=1e-4, want_mu=False):

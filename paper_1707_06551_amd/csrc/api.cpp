@@ -47,18 +47,27 @@ void apply(bie_ctx* c, int op, int precision, const double* mu, double* u) {
   if (stages == 0) stages = BIE_STAGE_SELF | BIE_STAGE_NEAR | BIE_STAGE_FAR;
   if (precision != BIE_FP64 && precision != BIE_MIXED) throw Error{BIE_EINVAL, "bad precision"};
   const OpSpec spec = op_spec(base);
+  if (spec.traction && c->near_method != 0)
+    throw Error{BIE_EINVAL, "the traction operator supports near_method 0 (series at the target nodes) only"};
   VshCall v;
   v.mu = mu;
   v.u = u;
   v.write_q = (stages & BIE_STAGE_FAR) != 0;
   v.write_coef = (stages & BIE_STAGE_NEAR) != 0 && !c->near_idx.empty();
   v.do_self = (stages & BIE_STAGE_SELF) != 0;
-  v.want_moments = spec.completion && (stages & BIE_STAGE_FAR);
+  v.want_moments = (spec.completion && (stages & BIE_STAGE_FAR)) || (spec.rigid_local && (stages & BIE_STAGE_SELF));
   v.bordered = spec.bordered;
   v.c_identity = spec.c_identity;
   self_lambda(spec, c->p, v.lam);
   launch_vsh(c, precision, v);
-  if (stages & BIE_STAGE_NEAR) launch_near(c, spec, u);
+  // L of Eq. 5.8 on the own sphere: int mu + (int (y - c) x mu) x (x - c)
+  if (spec.rigid_local && (stages & BIE_STAGE_SELF)) add_rigid_local(c, c->moments.as<double>(), u);
+  if (stages & BIE_STAGE_NEAR) {
+    if (spec.traction)
+      launch_near_traction(c, u);
+    else
+      launch_near(c, spec, u);
+  }
   if (stages & BIE_STAGE_FAR) launch_far(c, precision, spec, u);
 }
 
@@ -71,6 +80,9 @@ void apply(bie_ctx* c, int op, int precision, const double* mu, double* u) {
 //    V_1: 5/3, W_1: 3/2 with V'_1 += 5/12 W_1, X_1: 3; elsewhere 1 / D_+.
 //  - mobility form 1/2 + S + D_pv = S + D_+ ((n+1)/(2n+1) on V, W; n/(2n+1) on X),
 //    plus the rigid-body rows solved in closed form (see the transform kernel).
+//  - traction form of Eq. 5.8, 1/2 + K_pv + L: K_pv = D_pv on the sphere, so the
+//    eigenvalues are D_+'s; L acts on the rigid modes only, W_1[a] = a -> 4 pi a and
+//    X_1 (rotations) -> 8 pi / 3, which replace the zeros of D_+ there.
 void dev_precond_m0(bie_ctx* c, int op_base, int precision, const double* r, double* z) {
   VshCall v;
   v.mu = r;
@@ -89,6 +101,10 @@ void dev_precond_m0(bie_ctx* c, int op_base, int precision, const double* r, dou
           if (n == 1 && f == 0) inv = 5.0 / 3.0;
           else if (n == 1 && f == 1) inv = 1.5;
           else if (n == 1 && f == 2) inv = 3.0;
+          else inv = 1.0 / ed[f];
+        } else if (op_base == BIE_OP_KL_BIE) {
+          if (n == 1 && f == 1) inv = 1.0 / (4.0 * M_PI);
+          else if (n == 1 && f == 2) inv = 3.0 / (8.0 * M_PI);
           else inv = 1.0 / ed[f];
         } else {
           inv = 1.0 / (es[f] + ed[f]);
@@ -110,8 +126,11 @@ void apply_precond(bie_ctx* c, int op_base, int precision, int precond, const do
       lap_precond(c, r, z);
     return;
   }
-  if (op_base != BIE_OP_DN_BIE && op_base != BIE_OP_MOBILITY && op_base != BIE_OP_SD_BIE)
-    throw Error{BIE_EINVAL, "preconditioners exist for BIE_OP_DN_BIE, BIE_OP_MOBILITY and BIE_OP_SD_BIE"};
+  if (op_base != BIE_OP_DN_BIE && op_base != BIE_OP_MOBILITY && op_base != BIE_OP_SD_BIE && op_base != BIE_OP_KL_BIE)
+    throw Error{BIE_EINVAL,
+                "preconditioners exist for BIE_OP_DN_BIE, BIE_OP_MOBILITY, BIE_OP_SD_BIE and BIE_OP_KL_BIE"};
+  if (op_base == BIE_OP_KL_BIE && (precond & ~BIE_PC_M0) != 0)
+    throw Error{BIE_EINVAL, "BIE_OP_KL_BIE takes BIE_PC_NONE or BIE_PC_M0"};
   if (precision != BIE_FP64 && precision != BIE_MIXED) throw Error{BIE_EINVAL, "bad precision"};
   const int64_t n = 3 * c->N + (op_base == BIE_OP_MOBILITY ? 6 * c->nb : 0);
   const bool rigid = (precond & BIE_PC_RIGID) != 0;
@@ -137,7 +156,7 @@ void apply_precond(bie_ctx* c, int op_base, int precision, int precond, const do
   // of M0 r.  The learned close-pair correction acts on the density part of the
   // resistance and mobility forms (weights are trained per form) and is added last, so
   // that a network trained on a base keeps its rigid-mode output.
-  if (op_base == BIE_OP_SD_BIE) return;
+  if (op_base == BIE_OP_SD_BIE || op_base == BIE_OP_KL_BIE) return;
   if (rigid && op_base == BIE_OP_DN_BIE) rigid_correct(c, r, z);
   if (base == BIE_PC_MLP) coarse_correct(c, r, z);
 }
@@ -356,13 +375,65 @@ int bie_solve_mobility(bie_ctx* c, const double* F, const double* T, const doubl
   return rc;
 }
 
+int bie_solve_mobility_traction(bie_ctx* c, const double* F, const double* T, const bie_solve_opts* opts, double* v,
+                                double* omega, double* mu, bie_solve_info* info) {
+  if (!c || !F || !T || !v || !omega) {
+    bie::set_error("null argument");
+    return BIE_EINVAL;
+  }
+  if (opts && (opts->precond & ~BIE_PC_M0) != 0) {
+    bie::set_error("bie_solve_mobility_traction takes BIE_PC_NONE or BIE_PC_M0");
+    return BIE_EINVAL;
+  }
+  int rc = BIE_OK;
+  BIE_TRY({
+    const int64_t n3 = 3 * c->N, nb = c->nb;
+    bie::DevBuf rho, rhs, x, ab;
+    rho.alloc(n3 * sizeof(double));
+    rhs.alloc(n3 * sizeof(double));
+    x.alloc(n3 * sizeof(double));
+    ab.alloc(6 * nb * sizeof(double));
+    // rho of Eq. 5.7: F_k / (4 pi) + 3/(8 pi) T_k x (x - c_k)
+    std::vector<double> h(6 * nb);
+    for (int64_t k = 0; k < nb; ++k)
+      for (int d = 0; d < 3; ++d) {
+        h[6 * k + d] = F[3 * k + d] / (4.0 * M_PI);
+        h[6 * k + 3 + d] = 3.0 * T[3 * k + d] / (8.0 * M_PI);
+      }
+    BIE_HIP(hipMemcpyAsync(ab.ptr, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    bie::dev_fill(c, rho.as<double>(), 0.0, n3);
+    bie::add_rigid_local(c, ab.as<double>(), rho.as<double>());
+    // right-hand side of Eq. 5.8: -(1/2 rho + sum_k K_k[rho]), float64
+    bie::apply(c, BIE_OP_K, BIE_FP64, rho.as<double>(), rhs.as<double>());
+    bie::dev_axpby(c, -0.5, rho.as<double>(), -1.0, rhs.as<double>(), n3);
+    rc = bie::solve(c, BIE_OP_KL_BIE, rhs.as<double>(), x.as<double>(), n3, opts, info);
+    if (mu) BIE_HIP(hipMemcpyAsync(mu, x.ptr, n3 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    // u = sum_k S_k[mu + rho] on the surfaces (Eq. 5.7), its rigid motion per sphere
+    bie::dev_axpby(c, 1.0, rho.as<double>(), 1.0, x.as<double>(), n3);
+    bie::apply(c, BIE_OP_S, BIE_FP64, x.as<double>(), rhs.as<double>());
+    bie::rigid_restrict(c, rhs.as<double>(), ab.as<double>());
+    BIE_HIP(hipMemcpyAsync(h.data(), ab.ptr, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    BIE_HIP(hipStreamSynchronize(c->stream));
+    for (int64_t k = 0; k < nb; ++k)
+      for (int d = 0; d < 3; ++d) {
+        v[3 * k + d] = h[6 * k + d];
+        omega[3 * k + d] = h[6 * k + 3 + d];
+      }
+    rho.release();
+    rhs.release();
+    x.release();
+    ab.release();
+  });
+  return rc;
+}
+
 int bie_solve(bie_ctx* c, int op, const double* b, double* x, const bie_solve_opts* opts, bie_solve_info* info) {
   if (!c || !b || !x) {
     bie::set_error("null argument");
     return BIE_EINVAL;
   }
-  if (op != BIE_OP_DN_BIE && op != BIE_OP_MOBILITY && op != BIE_OP_SD_BIE) {
-    bie::set_error("bie_solve supports BIE_OP_DN_BIE, BIE_OP_MOBILITY and BIE_OP_SD_BIE");
+  if (op != BIE_OP_DN_BIE && op != BIE_OP_MOBILITY && op != BIE_OP_SD_BIE && op != BIE_OP_KL_BIE) {
+    bie::set_error("bie_solve supports BIE_OP_DN_BIE, BIE_OP_MOBILITY, BIE_OP_SD_BIE and BIE_OP_KL_BIE");
     return BIE_EINVAL;
   }
   int rc = BIE_OK;

@@ -45,6 +45,8 @@ struct DevBuf {
 struct OpSpec {
   double a_s, a_d, c_identity;
   bool completion, bordered;
+  bool traction = false;  // the single-layer traction K (target normal) instead of a_D D
+  bool rigid_local = false;  // + L: int mu + (int (y - c) x mu) x (x - c) on the own sphere
 };
 OpSpec op_spec(int op_base);
 
@@ -113,6 +115,10 @@ struct bie_ctx {
   bie::DevBuf nearcoef;             // nb x 3 x ncoef x 2: summed near-field coefficients
   bie::DevBuf tlat_d;               // nlat cos(theta_j)
 
+  // single-layer traction near series (traction.hip): recurrence table of degree p+1
+  bie::DevBuf rec2;
+  int mm2 = 0, ncoef2 = 0;
+
   // Laplace single layer and the magnetostatic problem (laplace.hip)
   bie::DevBuf lapcoef;              // nb x ncoef x 2 scalar coefficients
   double lap_eta = 0.0;             // eta of Eq. 5.13 for the current solve
@@ -162,6 +168,12 @@ void coarse_correct(bie_ctx* c, const double* r, double* z);
 // global rigid-mode coarse correction: z <- z + P (A_c^-1 R r - R z)
 constexpr int64_t RIGID_MAX_SPHERES = 65536;
 void rigid_correct(bie_ctx* c, const double* r, double* z);
+// xi[6k..6k+5] = ((1/4pi) int_k f, (3/8pi) int_k (x - c_k) x f): rigid motion of a field
+void rigid_restrict(bie_ctx* c, const double* f, double* xi);
+
+// single-layer traction K on the near pairs; u += a_k + b_k x (x - c_k) (ab = nb x 6)
+void launch_near_traction(bie_ctx* c, double* u);
+void add_rigid_local(bie_ctx* c, const double* ab, double* u);
 
 // Laplace / magnetostatic operators (laplace.hip); OP_LAPLACE is the solver's internal
 // operator code for (1/2 I + eta K^L) on N scalar unknowns

@@ -65,13 +65,16 @@ struct R4 {
   R x, y, z, w;
 };
 
-// KIND: 1 = Stokeslet, 2 = double layer, 3 = Stokeslet + double layer.  Constants:
+// KIND: 1 = Stokeslet, 2 = double layer, 3 = Stokeslet + double layer, 4 = single-layer
+// traction K (Eq. 2.22, normal of the TARGET node).  Constants:
 //   S:   (1/8pi) [q/r + r (r.q)/r^3]            -> c = (r.q) / r^3
 //   D:   (3/4pi) r (r.q)(r.n)/r^5               -> c = (r.q)(r.n) / r^5
 //   S+D: (1/8pi) [q/r + r (r.q)/r^3 (1 + 6 (r.n)/r^2)]  -> c = (r.q)/r^3 (3 (|p|^2 - 1)/r^2 - 2)
+//   K:   -(3/4pi) r (r.q)(r.n_x)/r^5            -> c = (r.q)(r.n_x) / r^5, with
+//        r.n_x = p.n_x - o.n_x and K3 = p.n_x formed once per (target, source sphere)
 template <typename R, int KIND>
-__device__ __forceinline__ void pair(R px, R py, R pz, R K, R K3, const R4<R>& o, const R4<R>& q, R& C, R& Cx, R& Cy,
-                                     R& Cz, R& Qx, R& Qy, R& Qz) {
+__device__ __forceinline__ void pair(R px, R py, R pz, R K, R K3, R tnx, R tny, R tnz, const R4<R>& o,
+                                     const R4<R>& q, R& C, R& Cx, R& Cy, R& Cz, R& Qx, R& Qy, R& Qz) {
   const R d = fma(pz, o.z, fma(py, o.y, px * o.x));
   const R r2 = fma((R)-2, d, K);
   const R ir = rsqrt_r<R>(r2);
@@ -83,6 +86,9 @@ __device__ __forceinline__ void pair(R px, R py, R pz, R K, R K3, const R4<R>& o
   } else if (KIND == 2) {
     const R rn = d - (R)1;
     c = (rq * rn) * (ir2 * ir2 * ir);
+  } else if (KIND == 4) {
+    const R rn = K3 - fma(o.z, tnz, fma(o.y, tny, o.x * tnx));
+    c = (rq * rn) * (ir2 * ir2 * ir);
   } else {
     const R t = fma(K3, ir2, (R)-2);   // 1 + 6 (r.n)/r^2 with K3 = 3 (|p|^2 - 1)
     c = ((rq * ir) * ir2) * t;
@@ -91,7 +97,7 @@ __device__ __forceinline__ void pair(R px, R py, R pz, R K, R K3, const R4<R>& o
   Cx = fma(c, o.x, Cx);
   Cy = fma(c, o.y, Cy);
   Cz = fma(c, o.z, Cz);
-  if (KIND != 2) {
+  if (KIND == 1 || KIND == 3) {
     Qx = fma(ir, q.x, Qx);
     Qy = fma(ir, q.y, Qy);
     Qz = fma(ir, q.z, Qz);
@@ -164,7 +170,10 @@ __global__ __launch_bounds__(256) void far_kernel(FarParams a) {
       py[k] = (R)dy + oxt[k][1];
       pz[k] = (R)dz + oxt[k][2];
       K[k] = fma(px[k], px[k], fma(py[k], py[k], fma(pz[k], pz[k], (R)1)));
-      K3[k] = (R)3 * fma(px[k], px[k], fma(py[k], py[k], fma(pz[k], pz[k], (R)-1)));
+      if (KIND == 4)
+        K3[k] = fma(px[k], oxt[k][0], fma(py[k], oxt[k][1], pz[k] * oxt[k][2]));
+      else
+        K3[k] = (R)3 * fma(px[k], px[k], fma(py[k], py[k], fma(pz[k], pz[k], (R)-1)));
       any = any || !skip[k];
       if (a.completion && valid[k]) {
         // Stokeslet of strength F_s and rotlet of torque T_s at c_s, in float64
@@ -202,7 +211,8 @@ __global__ __launch_bounds__(256) void far_kernel(FarParams a) {
       }
 #pragma unroll
       for (int k = 0; k < TPL; ++k)
-        pair<R, KIND>(px[k], py[k], pz[k], K[k], K3[k], o, qq, C[k], Cx[k], Cy[k], Cz[k], Qx[k], Qy[k], Qz[k]);
+        pair<R, KIND>(px[k], py[k], pz[k], K[k], K3[k], oxt[k][0], oxt[k][1], oxt[k][2], o, qq, C[k], Cx[k], Cy[k],
+                      Cz[k], Qx[k], Qy[k], Qz[k]);
     }
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
@@ -268,18 +278,20 @@ void launch_far(bie_ctx* c, int precision, const OpSpec& spec, double* u) {
   a.sph_per_split = (int)((c->nb + c->nsplit - 1) / c->nsplit);
   a.completion = spec.completion ? 1 : 0;
   const int nsplit = (int)((c->nb + a.sph_per_split - 1) / a.sph_per_split);
-  const int kind = (spec.a_s != 0.0 ? 1 : 0) + (spec.a_d != 0.0 ? 2 : 0);
-  a.cscale = (kind == 2) ? 3.0 / (4.0 * M_PI) : 1.0 / (8.0 * M_PI);
+  const int kind = spec.traction ? 4 : (spec.a_s != 0.0 ? 1 : 0) + (spec.a_d != 0.0 ? 2 : 0);
+  a.cscale = (kind == 2) ? 3.0 / (4.0 * M_PI) : (kind == 4) ? -3.0 / (4.0 * M_PI) : 1.0 / (8.0 * M_PI);
   dim3 grid((unsigned)((c->N + 256 * TPL - 1) / (256 * TPL)), (unsigned)nsplit);
   if (kind == 0) throw Error{BIE_EINVAL, "empty far-field kernel"};
   if (f32) {
     if (kind == 1) far_launch<float, 1>(c, a, grid);
     if (kind == 2) far_launch<float, 2>(c, a, grid);
     if (kind == 3) far_launch<float, 3>(c, a, grid);
+    if (kind == 4) far_launch<float, 4>(c, a, grid);
   } else {
     if (kind == 1) far_launch<double, 1>(c, a, grid);
     if (kind == 2) far_launch<double, 2>(c, a, grid);
     if (kind == 3) far_launch<double, 3>(c, a, grid);
+    if (kind == 4) far_launch<double, 4>(c, a, grid);
   }
   BIE_HIP(hipGetLastError());
   const int64_t n3 = 3 * c->N;

@@ -264,6 +264,12 @@ __global__ void k_unscale(const double* x, int64_t n, double* y) {
 
 }  // namespace
 
+void rigid_restrict(bie_ctx* c, const double* f, double* xi) {
+  k_rigid_restrict<<<dim3((unsigned)c->nb), dim3(256), 0, c->stream>>>(f, c->frame.as<double>(),
+                                                                      c->wnode.as<double>(), c->P, xi);
+  BIE_HIP(hipGetLastError());
+}
+
 void rigid_correct(bie_ctx* c, const double* r, double* z) {
   const int64_t nb = c->nb, n = 6 * nb;
   if (nb > RIGID_MAX_SPHERES) throw Error{BIE_EINVAL, "BIE_PC_RIGID: too many spheres for the coarse solve"};

@@ -39,6 +39,9 @@ OpSpec op_spec(int op_base) {
     case BIE_OP_SD_BIE: return {1.0, 1.0, 0.5, false, false};
     case BIE_OP_DN_BIE: return {0.0, 1.0, 0.5, true, false};
     case BIE_OP_MOBILITY: return {1.0, 1.0, 0.5, false, true};
+    // K: self K_pv = D_pv on every mode (Table 3.12), so the self multipliers are a_D's
+    case BIE_OP_K: return {0.0, 1.0, 0.0, false, false, true, false};
+    case BIE_OP_KL_BIE: return {0.0, 1.0, 0.5, false, false, true, true};
     default: throw Error{BIE_EINVAL, "unknown operator " + std::to_string(op_base)};
   }
 }
@@ -105,6 +108,40 @@ static double alpha_nm(int n, int m) {
 }
 static double beta_nm(int n, int m) {
   return std::sqrt((n + 1.0) * (n + 1.0) * ((double)n * n - (double)m * m) / ((2.0 * n + 1.0) * (2.0 * n - 1.0)));
+}
+
+// Recurrence constants per coefficient slot (m, n), slots ordered by m (0..mmax) then n
+// (m..p), for the series evaluations at arbitrary points (series.h):
+//   A_{n,m} = sqrt((4n^2-1)/(n^2-m^2)), B_{n,m} = sqrt(((n-1)^2-m^2)/(4(n-1)^2-1)).
+//   m = 0:  [A_{n+1,0}, B_{n+1,0}, -sqrt(n(n+1)), 0, A_{n+2,1}, B_{n+2,1}]
+//   m >= 1: [A_{n+2,m}, B_{n+2,m}, alpha_n^m, beta_n^m, sqrt(2m+3), sqrt((2m+1)/(2m))]
+std::vector<double> recurrence_table(int p, int mmax) {
+  auto Anm = [](int n, int m) { return std::sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)m * m)); };
+  auto Bnm = [](int n, int m) {
+    return std::sqrt(((n - 1.0) * (n - 1.0) - (double)m * m) / (4.0 * (n - 1.0) * (n - 1.0) - 1.0));
+  };
+  std::vector<double> rec;
+  for (int m = 0; m <= mmax; ++m)
+    for (int n = m; n <= p; ++n) {
+      double r[6];
+      if (m == 0) {
+        r[0] = Anm(n + 1, 0);
+        r[1] = Bnm(n + 1, 0);
+        r[2] = -std::sqrt((double)n * (n + 1.0));
+        r[3] = 0.0;
+        r[4] = Anm(n + 2, 1);
+        r[5] = Bnm(n + 2, 1);
+      } else {
+        r[0] = Anm(n + 2, m);
+        r[1] = Bnm(n + 2, m);
+        r[2] = alpha_nm(n, m);
+        r[3] = beta_nm(n, m);
+        r[4] = std::sqrt(2.0 * m + 3.0);
+        r[5] = std::sqrt((2.0 * m + 1.0) / (2.0 * m));
+      }
+      rec.insert(rec.end(), r, r + 6);
+    }
+  return rec;
 }
 
 // Table at one latitude: Pbar_n^m, dPbar_n^m/dtheta, m Pbar_n^m / sin(theta).
@@ -331,34 +368,7 @@ void build(bie_ctx* c, const double* centres, int64_t nb, const bie_opts* o) {
     modes[2 * i] = c->coef_m[i];
     modes[2 * i + 1] = c->coef_n[i];
   }
-  // recurrence constants per coefficient slot (m, n) for the near-series kernel:
-  //   A_{n,m} = sqrt((4n^2-1)/(n^2-m^2)), B_{n,m} = sqrt(((n-1)^2-m^2)/(4(n-1)^2-1)).
-  //   m = 0:  [A_{n+1,0}, B_{n+1,0}, -sqrt(n(n+1)), 0, A_{n+2,1}, B_{n+2,1}]
-  //   m >= 1: [A_{n+2,m}, B_{n+2,m}, alpha_n^m, beta_n^m, sqrt(2m+3), sqrt((2m+1)/(2m))]
-  auto Anm = [](int n, int m) { return std::sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)m * m)); };
-  auto Bnm = [](int n, int m) {
-    return std::sqrt(((n - 1.0) * (n - 1.0) - (double)m * m) / (4.0 * (n - 1.0) * (n - 1.0) - 1.0));
-  };
-  std::vector<double> rec(6 * (size_t)nc, 0.0);
-  for (int i = 0; i < nc; ++i) {
-    const int m = c->coef_m[i], n = c->coef_n[i];
-    double* r = &rec[6 * (size_t)i];
-    if (m == 0) {
-      r[0] = Anm(n + 1, 0);
-      r[1] = Bnm(n + 1, 0);
-      r[2] = -std::sqrt((double)n * (n + 1.0));
-      r[3] = 0.0;
-      r[4] = Anm(n + 2, 1);
-      r[5] = Bnm(n + 2, 1);
-    } else {
-      r[0] = Anm(n + 2, m);
-      r[1] = Bnm(n + 2, m);
-      r[2] = alpha_nm(n, m);
-      r[3] = beta_nm(n, m);
-      r[4] = std::sqrt(2.0 * m + 3.0);
-      r[5] = std::sqrt((2.0 * m + 1.0) / (2.0 * m));
-    }
-  }
+  std::vector<double> rec = recurrence_table(c->p, c->mmax);
   auto tof = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
 
   // ---- device upload -------------------------------------------------------------

@@ -138,7 +138,7 @@ struct Krylov {
 // Operator application used by the solver: y = A M x (M = preconditioner or identity)
 struct OpCtx {
   bie_ctx* c;
-  int op;           // BIE_OP_DN_BIE, BIE_OP_MOBILITY or BIE_OP_SD_BIE
+  int op;           // BIE_OP_DN_BIE, BIE_OP_MOBILITY, BIE_OP_SD_BIE or BIE_OP_KL_BIE
   int precision;    // matvec precision inside this Krylov solve
   int precond;      // BIE_PC_*
   int* matvecs64;

@@ -3,7 +3,9 @@
 near series and far field together) as the lattice grows from 2^3 to 17^3 unit spheres,
 loosely (q = 1) and densely (q = 4) packed, at p = 4 and 8.
 
-The paper evaluates its far field with an FMM and reports slopes approaching 1 in
+The paper times the double layer D and the single-layer traction K (--op k), whose
+near evaluation carries the extra terms of the target normal.  The paper evaluates its
+far field with an FMM and reports slopes approaching 1 in
 log(time) against log(n_b); the far field here is an all-pairs sum, so the slope tends
 to 2 once the far field dominates.  One JSON line per case, then the slopes.
 
@@ -18,7 +20,7 @@ import numpy as np
 from . import bie
 from .inputs import lattice_centres
 
-OPS = {"s": bie.OP_S, "d": bie.OP_D, "sd": bie.OP_SD_BIE, "dn": bie.OP_DN_BIE}
+OPS = {"s": bie.OP_S, "d": bie.OP_D, "sd": bie.OP_SD_BIE, "dn": bie.OP_DN_BIE, "k": bie.OP_K}
 
 
 def time_apply(sph, op, precision, reps):
