@@ -98,6 +98,20 @@ typedef struct {
  * until the upload completes.  *out is owned by the caller and released by bie_free. */
 int bie_build_spheres(const double* centres, int64_t n_spheres, const bie_opts* opts, bie_ctx** out);
 
+/* As bie_build_spheres for spheres of radii a_k (host, n_spheres, each in [1/16, 16];
+ * NULL = all 1): polydisperse suspensions (Section 6, Figs. 4 (a), 8 (c)-(d)).  Node
+ * x = c_k + a_k xhat with weight a_k^2 w (Eq. 4.4 scaled); the single layer on a sphere
+ * of radius a scales with a (Table 3.12 eigenvalues times a, exterior series of
+ * Eqs. 3.6-3.8 at (x - c)/a times a), the double layer and the traction K not at all.
+ * Near pairs: |c_t - c_s| - a_t - a_s < near_gap * a_s (Eq. 4.5 with the gap measured in
+ * the source's radius; directed).  Overlap: |c_t - c_s| < a_t + a_s -> BIE_EOVERLAP.  When
+ * some radius differs from 1 the context supports bie_apply_bio with BIE_OP_S, _D,
+ * _SD_BIE and _K, bie_solve with BIE_OP_SD_BIE (porous media, Problem 1) and BIE_PC_NONE
+ * or BIE_PC_M0 (1 / (a lambda_S + lambda_D+) per mode), the transforms, nodes and near
+ * pairs; every other entry point returns BIE_EINVAL, as does near_method 1. */
+int bie_build_spheres_radii(const double* centres, const double* radii, int64_t n_spheres, const bie_opts* opts,
+                            bie_ctx** out);
+
 void bie_free(bie_ctx* ctx);
 
 /* Number of nodes N; number of spheres; P per sphere; mmax.  Host outputs. */

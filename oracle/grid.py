@@ -55,14 +55,18 @@ def sphere_grid(p, n_phi=None):
 
 
 class Geometry:
-    """n_b unit spheres with the grid of Eq. 4.2 on each.
+    """n_b spheres with the grid of Eq. 4.2 on each (unit radius unless ``radii`` given).
 
     Node order: g = k * P + j * n_phi + l (sphere k, latitude j, longitude l).
     ``near_gap`` is the separation threshold d* of Eq. 4.5 written as a surface gap:
-    spheres s != t are "near" when |c_t - c_s| - 2 < d*.
+    spheres s != t are "near" when |c_t - c_s| - 2 < d*.  With radii a_k (polydisperse
+    suspensions, Section 6), node x = c_k + a_k xhat, weight a_k^2 w, and the gap is
+    measured in units of the source radius: near[t, s] when
+    |c_t - c_s| - a_t - a_s < d* a_s (the far quadrature of sphere s resolves distances
+    on the scale of its own node spacing, a_s / p).
     """
 
-    def __init__(self, centres, p, n_phi=None, near_gap=1.0):
+    def __init__(self, centres, p, n_phi=None, near_gap=1.0, radii=None):
         self.centres = np.ascontiguousarray(centres, dtype=np.float64).reshape(-1, 3)
         self.nb = self.centres.shape[0]
         self.grid = sphere_grid(p, n_phi)
@@ -72,14 +76,17 @@ class Geometry:
         self.P = (p + 1) * self.n_phi
         self.N = self.nb * self.P
         self.near_gap = float(near_gap)
+        self.radii = np.ones(self.nb) if radii is None else np.asarray(radii, dtype=np.float64).reshape(-1)
+        self.unit = bool(np.all(self.radii == 1.0))
+        a = self.radii
         xh = self.grid["xhat"]
         self.xhat = np.tile(xh, (self.nb, 1))                     # outward normals
-        self.nodes = (self.centres[:, None, :] + xh[None, :, :]).reshape(-1, 3)
-        self.w = np.tile(self.grid["wnode"], self.nb)
+        self.nodes = (self.centres[:, None, :] + a[:, None, None] * xh[None, :, :]).reshape(-1, 3)
+        self.w = (a[:, None] ** 2 * self.grid["wnode"][None, :]).reshape(-1)
         self.sphere_of = np.repeat(np.arange(self.nb), self.P)
         d = np.linalg.norm(self.centres[:, None, :] - self.centres[None, :, :], axis=-1)
         self.centre_dist = d
-        near = (d < 2.0 + self.near_gap)
+        near = (d - a[:, None] - a[None, :] < self.near_gap * a[None, :])
         np.fill_diagonal(near, False)
         self.near = near                                          # near[t, s]
 

@@ -70,11 +70,13 @@ class Operators:
 
     # ---- the three parts -----------------------------------------------------------
     def self_part(self, mu, a_s, a_d, spheres=None):
-        """Self term on every sphere (or only on `spheres`; other entries stay 0)."""
+        """Self term on every sphere (or only on `spheres`; other entries stay 0).  On a
+        sphere of radius a the single layer scales with a (its kernel is homogeneous of
+        degree -1 and the area element of degree 2), the double layer not at all."""
         mu, batch = self._as_batch(mu)
-        lam = self.eigen_scale(a_s, a_d)[..., None]
         out = np.zeros_like(mu)
         for k in (range(self.g.nb) if spheres is None else spheres):
+            lam = self.eigen_scale(a_s * self.g.radii[k], a_d)[..., None]
             sl = self.g.sphere_nodes(k)
             out[sl] = self.vsh.inverse(lam * self.vsh.forward(mu[sl]))
         return out if batch else out[..., 0]
@@ -100,11 +102,13 @@ class Operators:
             out[rows] = kernels.direct_sum(g.nodes[tg[rows]], g.nodes[src], g.xhat[src], q[src], a_s, a_d)
         return out if batch else out[..., 0]
 
-    def near_field_from(self, coef, centre, x, a_s, a_d):
+    def near_field_from(self, coef, centre, x, a_s, a_d, radius=1.0):
         """Exterior series (Eqs. 3.6-3.11) of the layer potential a_S S + a_D D of a
-        density with VSH coefficients coef (3, M, B) on the unit sphere at `centre`,
-        evaluated at points x (K, 3) outside it."""
-        d = x - centre[None, :]
+        density with VSH coefficients coef (3, M, B) on the sphere of radius `radius`
+        at `centre`, evaluated at points x (K, 3) outside it (in units of the radius,
+        the single layer scaled by it)."""
+        a_s = a_s * radius
+        d = (x - centre[None, :]) / radius
         r = np.linalg.norm(d, axis=1)
         modes, _Y, V, W, X = vsh_at(d / r[:, None], self.g.p, self.g.mmax)
         out = np.zeros((x.shape[0], 3, coef.shape[2]), dtype=np.complex128)
@@ -132,14 +136,16 @@ class Operators:
             for s in np.nonzero(g.near[t])[0]:
                 if s not in cache:
                     cache[s] = self.coefficients(mu, s)
-                out[rows] += self.near_field_from(cache[s], g.centres[s], g.nodes[tg[rows]], a_s, a_d)
+                out[rows] += self.near_field_from(cache[s], g.centres[s], g.nodes[tg[rows]], a_s, a_d, g.radii[s])
         return out if batch else out[..., 0]
 
     def moments(self, mu):
         """Per sphere: F_k = sum w mu, T_k = sum w (y - c_k) x mu  (quadrature, Eq. 4.4).
-        Returns (nb, 3, B), (nb, 3, B)."""
+        Returns (nb, 3, B), (nb, 3, B).  Unit spheres."""
         mu, _ = self._as_batch(mu)
         g = self.g
+        if not g.unit:
+            raise NotImplementedError("moments, completion and bordered rows are for unit spheres")
         wm = mu * g.w[:, None, None]
         F = wm.reshape(g.nb, g.P, 3, -1).sum(axis=1)
         o = g.xhat[:, :, None]

@@ -254,7 +254,8 @@ class TractionOps:
             rows = g.sphere_nodes(t)
             for s in np.nonzero(g.near[t])[0]:
                 coef = self.ops.vsh.forward(mu[g.sphere_nodes(s)])[..., None]
-                d = g.nodes[rows] - g.centres[s][None, :]
+                # traction is scale invariant: evaluate in units of the source radius
+                d = (g.nodes[rows] - g.centres[s][None, :]) / g.radii[s]
                 out[rows] += single_layer_traction(coef, g.p, g.mmax, d, g.xhat[rows])[..., 0]
         return out
 

@@ -26,7 +26,7 @@ EXPORTED = [
     "bie_vsh_forward", "bie_vsh_inverse", "bie_solve_resistance", "bie_solve_mobility", "bie_last_error",
     "bie_solve", "bie_apply_precond", "bie_lowmodes", "bie_lowmodes_synth", "bie_pair_geometry",
     "bie_mlp_n_weights", "bie_precond_load", "bie_mlp_eval", "bie_mlp_train", "bie_eval_field",
-    "bie_apply_laplace", "bie_solve_magnetic", "bie_solve_mobility_traction",
+    "bie_apply_laplace", "bie_solve_magnetic", "bie_solve_mobility_traction", "bie_build_spheres_radii",
 ]
 NLOW = 25
 NFEAT = 8
@@ -74,6 +74,8 @@ def lib():
     P, I, I64, D, VP = ctypes.POINTER, ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
     L.bie_build_spheres.argtypes = [VP, I64, P(Opts), P(VP)]
     L.bie_build_spheres.restype = I
+    L.bie_build_spheres_radii.argtypes = [VP, VP, I64, P(Opts), P(VP)]
+    L.bie_build_spheres_radii.restype = I
     L.bie_free.argtypes = [VP]
     L.bie_free.restype = None
     L.bie_sizes.argtypes = [VP, P(I64), P(I64), P(I64), P(I64)]
@@ -207,9 +209,10 @@ def _dptr(t):
 
 
 class Spheres:
-    """A context for n_b unit spheres (bie_build_spheres)."""
+    """A context for n_b spheres (bie_build_spheres; bie_build_spheres_radii when radii
+    are given: polydisperse suspensions, a subset of the operators)."""
 
-    def __init__(self, centres, p, n_phi=0, near_gap=1.0, device=0, stream=None, near_method=0):
+    def __init__(self, centres, p, n_phi=0, near_gap=1.0, device=0, stream=None, near_method=0, radii=None):
         import torch
         L = lib()
         c = np.ascontiguousarray(centres, dtype=np.float64).reshape(-1, 3)
@@ -219,7 +222,13 @@ class Spheres:
         self.device = device
         o = Opts(p, n_phi, near_gap, device, ctypes.c_void_p(stream.cuda_stream), near_method)
         h = ctypes.c_void_p()
-        _check(L.bie_build_spheres(_hptr(c), c.shape[0], ctypes.byref(o), ctypes.byref(h)))
+        if radii is None:
+            _check(L.bie_build_spheres(_hptr(c), c.shape[0], ctypes.byref(o), ctypes.byref(h)))
+        else:
+            rad = np.ascontiguousarray(radii, dtype=np.float64).reshape(-1)
+            if rad.size != c.shape[0]:
+                raise ValueError("one radius per sphere")
+            _check(L.bie_build_spheres_radii(_hptr(c), _hptr(rad), c.shape[0], ctypes.byref(o), ctypes.byref(h)))
         self._h = h
         n, nb, P, mm = (ctypes.c_int64() for _ in range(4))
         _check(L.bie_sizes(h, ctypes.byref(n), ctypes.byref(nb), ctypes.byref(P), ctypes.byref(mm)))

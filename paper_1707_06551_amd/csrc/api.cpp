@@ -7,7 +7,7 @@
 #include "bie_internal.h"
 
 namespace bie {
-void build(bie_ctx* c, const double* centres, int64_t nb, const bie_opts* o);
+void build(bie_ctx* c, const double* centres, const double* radii, int64_t nb, const bie_opts* o);
 const char* last_error();
 
 // Table 3.12: S, D_+ eigenvalues per family (V, W, X) and degree n.
@@ -49,6 +49,8 @@ void apply(bie_ctx* c, int op, int precision, const double* mu, double* u) {
   const OpSpec spec = op_spec(base);
   if (spec.traction && c->near_method != 0)
     throw Error{BIE_EINVAL, "the traction operator supports near_method 0 (series at the target nodes) only"};
+  if (c->poly && (spec.completion || spec.bordered || spec.rigid_local))
+    throw Error{BIE_EINVAL, "spheres of several radii support BIE_OP_S, _D, _SD_BIE and _K only"};
   VshCall v;
   v.mu = mu;
   v.u = u;
@@ -58,7 +60,18 @@ void apply(bie_ctx* c, int op, int precision, const double* mu, double* u) {
   v.want_moments = (spec.completion && (stages & BIE_STAGE_FAR)) || (spec.rigid_local && (stages & BIE_STAGE_SELF));
   v.bordered = spec.bordered;
   v.c_identity = spec.c_identity;
-  self_lambda(spec, c->p, v.lam);
+  if (c->poly) {
+    // per-sphere multipliers: a_k a_S lambda_S + a_D lambda_Dpv
+    OpSpec ss = spec, sd = spec;
+    ss.a_d = 0.0;
+    sd.a_s = 0.0;
+    self_lambda(ss, c->p, v.lamS);
+    self_lambda(sd, c->p, v.lam);
+    v.radius = c->radius_d.as<double>();
+    v.lam_mode = 1;
+  } else {
+    self_lambda(spec, c->p, v.lam);
+  }
   launch_vsh(c, precision, v);
   // L of Eq. 5.8 on the own sphere: int mu + (int (y - c) x mu) x (x - c)
   if (spec.rigid_local && (stages & BIE_STAGE_SELF)) add_rigid_local(c, c->moments.as<double>(), u);
@@ -89,6 +102,24 @@ void dev_precond_m0(bie_ctx* c, int op_base, int precision, const double* r, dou
   v.u = z;
   v.do_self = true;
   v.c_identity = 2.0;
+  if (c->poly) {
+    // spheres of radius a_k, 1/2 + S + D_pv only: 1 / (a_k lambda_S + lambda_D+) per mode
+    if (op_base != BIE_OP_SD_BIE) throw Error{BIE_EINVAL, "spheres of several radii: M0 exists for BIE_OP_SD_BIE"};
+    for (int n = 0; n <= c->p; ++n) {
+      double es[3], ed[3];
+      eig_S(n, es);
+      eig_Dplus(n, ed);
+      for (int f = 0; f < 3; ++f) {
+        const bool exists = (f == 0) || n >= 1;
+        v.lamS[f][n] = exists ? es[f] : 0.0;
+        v.lam[f][n] = exists ? ed[f] : 0.0;
+      }
+    }
+    v.radius = c->radius_d.as<double>();
+    v.lam_mode = 2;
+    launch_vsh(c, precision, v);
+    return;
+  }
   for (int n = 0; n <= c->p; ++n) {
     double es[3], ed[3];
     eig_S(n, es);
@@ -135,6 +166,8 @@ void apply_precond(bie_ctx* c, int op_base, int precision, int precond, const do
   const int64_t n = 3 * c->N + (op_base == BIE_OP_MOBILITY ? 6 * c->nb : 0);
   const bool rigid = (precond & BIE_PC_RIGID) != 0;
   const int base = precond & ~BIE_PC_RIGID;
+  if (c->poly && (op_base != BIE_OP_SD_BIE || (precond & ~BIE_PC_M0) != 0))
+    throw Error{BIE_EINVAL, "spheres of several radii: preconditioners BIE_PC_NONE / BIE_PC_M0 of BIE_OP_SD_BIE only"};
   if (rigid && base == BIE_PC_NONE) throw Error{BIE_EINVAL, "BIE_PC_RIGID needs BIE_PC_M0 or BIE_PC_MLP"};
   if (rigid && c->nb > RIGID_MAX_SPHERES) throw Error{BIE_EINVAL, "BIE_PC_RIGID: too many spheres for the coarse solve"};
   switch (base) {
@@ -183,6 +216,11 @@ using bie::Error;
 extern "C" {
 
 int bie_build_spheres(const double* centres, int64_t n_spheres, const bie_opts* opts, bie_ctx** out) {
+  return bie_build_spheres_radii(centres, nullptr, n_spheres, opts, out);
+}
+
+int bie_build_spheres_radii(const double* centres, const double* radii, int64_t n_spheres, const bie_opts* opts,
+                            bie_ctx** out) {
   if (!out) {
     bie::set_error("out is NULL");
     return BIE_EINVAL;
@@ -192,7 +230,7 @@ int bie_build_spheres(const double* centres, int64_t n_spheres, const bie_opts* 
   if (!c) return BIE_ENOMEM;
   try {
     bie::clear_error();
-    bie::build(c, centres, n_spheres, opts);
+    bie::build(c, centres, radii, n_spheres, opts);
   } catch (const Error& e) {
     bie::set_error(e.msg);
     bie_free(c);
@@ -234,12 +272,13 @@ int bie_get_nodes(const bie_ctx* c, double* xyz, double* w) {
       const double tj = c->t[j], sj = std::sqrt(std::max(0.0, 1.0 - tj * tj));
       for (int l = 0; l < c->n_phi; ++l) {
         const int64_t g = k * c->P + j * c->n_phi + l;
+        const double a = c->radius[k];
         if (xyz) {
-          xyz[3 * g] = c->centres[3 * k] + sj * std::cos(c->phi[l]);
-          xyz[3 * g + 1] = c->centres[3 * k + 1] + sj * std::sin(c->phi[l]);
-          xyz[3 * g + 2] = c->centres[3 * k + 2] + tj;
+          xyz[3 * g] = c->centres[3 * k] + a * (sj * std::cos(c->phi[l]));
+          xyz[3 * g + 1] = c->centres[3 * k + 1] + a * (sj * std::sin(c->phi[l]));
+          xyz[3 * g + 2] = c->centres[3 * k + 2] + a * tj;
         }
-        if (w) w[g] = c->wlat[j];
+        if (w) w[g] = a * a * c->wlat[j];
       }
     }
   return BIE_OK;
@@ -305,6 +344,7 @@ int bie_solve_resistance(bie_ctx* c, const double* v, const double* omega, const
   }
   int rc = BIE_OK;
   BIE_TRY({
+    bie::require_unit(c, "bie_solve_resistance");
     const int64_t n = 3 * c->N;
     bie::DevBuf rhs, x, vw;
     rhs.alloc(n * sizeof(double));
@@ -344,6 +384,7 @@ int bie_solve_mobility(bie_ctx* c, const double* F, const double* T, const doubl
   }
   int rc = BIE_OK;
   BIE_TRY({
+    bie::require_unit(c, "bie_solve_mobility");
     const int64_t n3 = 3 * c->N, n = n3 + 6 * c->nb;
     bie::DevBuf rhs, x;
     rhs.alloc(n * sizeof(double));
@@ -387,6 +428,7 @@ int bie_solve_mobility_traction(bie_ctx* c, const double* F, const double* T, co
   }
   int rc = BIE_OK;
   BIE_TRY({
+    bie::require_unit(c, "bie_solve_mobility_traction");
     const int64_t n3 = 3 * c->N, nb = c->nb;
     bie::DevBuf rho, rhs, x, ab;
     rho.alloc(n3 * sizeof(double));
@@ -456,7 +498,7 @@ int bie_apply_laplace(bie_ctx* c, int kind, double eta, const double* q, double*
     bie::set_error("bie_apply_laplace: bad arguments");
     return BIE_EINVAL;
   }
-  BIE_TRY(if (kind == 0) {
+  BIE_TRY(bie::require_unit(c, "bie_apply_laplace"); if (kind == 0) {
     c->lap_eta = eta;
     bie::lap_apply(c, q, out);
   } else {
@@ -473,6 +515,7 @@ int bie_solve_magnetic(bie_ctx* c, const double* H0, double eta, const bie_solve
   }
   int rc = BIE_OK;
   BIE_TRY({
+    bie::require_unit(c, "bie_solve_magnetic");
     bie::DevBuf qtmp;
     double* qd = q;
     if (!qd) {
@@ -495,19 +538,19 @@ int bie_eval_field(bie_ctx* c, int op, const double* mu, int64_t n_targets, cons
     bie::set_error("null context");
     return BIE_EINVAL;
   }
-  BIE_TRY(bie::eval_field(c, op, mu, n_targets, targets, u));
+  BIE_TRY(bie::require_unit(c, "bie_eval_field"); bie::eval_field(c, op, mu, n_targets, targets, u));
   return BIE_OK;
 }
 
 int bie_lowmodes(bie_ctx* c, const double* f, double* rho) {
   if (!c || !f || !rho) return BIE_EINVAL;
-  BIE_TRY(bie::lowmode_restrict(c, f, rho));
+  BIE_TRY(bie::require_unit(c, "bie_lowmodes"); bie::lowmode_restrict(c, f, rho));
   return BIE_OK;
 }
 
 int bie_lowmodes_synth(bie_ctx* c, const double* rho, double* f) {
   if (!c || !f || !rho) return BIE_EINVAL;
-  BIE_TRY(bie::lowmode_prolong(c, rho, f, false));
+  BIE_TRY(bie::require_unit(c, "bie_lowmodes_synth"); bie::lowmode_prolong(c, rho, f, false));
   return BIE_OK;
 }
 
@@ -533,7 +576,7 @@ int bie_precond_load(bie_ctx* c, const float* weights, int64_t n_weights) {
     bie::set_error("null context / weights or wrong weight count");
     return BIE_EINVAL;
   }
-  BIE_TRY(bie::mlp_infer(c, weights));
+  BIE_TRY(bie::require_unit(c, "bie_precond_load"); bie::mlp_infer(c, weights));
   return BIE_OK;
 }
 

@@ -62,12 +62,15 @@ struct bie_ctx {
 
   // host copies
   std::vector<double> centres;  // nb x 3
+  std::vector<double> radius;   // nb sphere radii (all 1 unless built with radii)
+  bool poly = false;            // some radius differs from 1
   std::vector<double> t, lam, theta, wlat, phi;
   std::vector<int> near_ptr, near_idx;  // CSR, target sphere -> near source spheres
   std::vector<int> coef_m, coef_n, coef_off;  // mode (m, n) of each coefficient slot; slot of (m, m)
 
   // device: geometry
   bie::DevBuf centres4;   // nb x 4 double (x, y, z, 0)
+  bie::DevBuf radius_d;   // nb double radii (allocated when poly)
   bie::DevBuf excl;       // nb x nwords uint32: bit s of row t set if s == t or (t, s) near
   int nwords = 0;
   bie::DevBuf dnear_ptr, dnear_idx;
@@ -140,8 +143,16 @@ struct VshCall {
   bool accumulate = false;          // add the synthesis to u instead of overwriting it
   double c_identity = 0.0, scale_out = 1.0, wv1 = 0.0;
   double lam[3][33] = {};
+  // per-sphere multipliers for spheres of radius a_k (radius != nullptr):
+  //   lam_mode 1: a_k lamS + lam (operator);  2: 1 / (a_k lamS + lam) - 2 (M0), 0 where
+  //   both vanish
+  const double* radius = nullptr;
+  int lam_mode = 0;
+  double lamS[3][33] = {};
 };
 void launch_vsh(bie_ctx* c, int precision, const VshCall& v);
+// EINVAL unless every sphere has unit radius (features built for unit spheres only)
+void require_unit(const bie_ctx* c, const char* what);
 void launch_near(bie_ctx* c, const OpSpec& spec, double* u);
 void launch_near_rot(bie_ctx* c, const OpSpec& spec, double* u);
 void series_radial(double a_s, double a_d, int p, double* kvv, double* kww, double* kwv, double* kxx);

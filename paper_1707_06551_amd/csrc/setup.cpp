@@ -228,7 +228,11 @@ static void upload_vec(DevBuf& b, const std::vector<T>& v) {
   upload(b, v.data(), v.size() * sizeof(T));
 }
 
-void build(bie_ctx* c, const double* centres, int64_t nb, const bie_opts* o) {
+void require_unit(const bie_ctx* c, const char* what) {
+  if (c->poly) throw Error{BIE_EINVAL, std::string(what) + " is built for unit spheres only"};
+}
+
+void build(bie_ctx* c, const double* centres, const double* radii, int64_t nb, const bie_opts* o) {
   if (!centres || nb <= 0 || !o) throw Error{BIE_EINVAL, "null centres/opts or no spheres"};
   if (o->p < 1 || o->p > 20) throw Error{BIE_EINVAL, "p must be in [1, 20]"};
   int nphi = o->n_phi > 0 ? o->n_phi : 2 * o->p;
@@ -250,9 +254,28 @@ void build(bie_ctx* c, const double* centres, int64_t nb, const bie_opts* o) {
   c->centres.assign(centres, centres + 3 * nb);
   for (double x : c->centres)
     if (!std::isfinite(x)) throw Error{BIE_EINVAL, "non-finite centre coordinate"};
+  c->radius.assign(nb, 1.0);
+  if (radii) {
+    for (int64_t k = 0; k < nb; ++k) {
+      const double a = radii[k];
+      if (!(a >= 1.0 / 16.0 && a <= 16.0)) throw Error{BIE_EINVAL, "radii must lie in [1/16, 16]"};
+      c->radius[k] = a;
+    }
+  }
+  double amax = 0.0;
+  c->poly = false;
+  for (double a : c->radius) {
+    amax = std::max(amax, a);
+    if (a != 1.0) c->poly = true;
+  }
+  const double* rad = c->radius.data();
+  if (c->poly && c->near_method != 0)
+    throw Error{BIE_EINVAL, "near_method 1 (pole rotation) is built for unit spheres only"};
 
   // ---- near pairs (Eq. 4.5 as a surface-gap test) with a uniform cell list --------
-  const double cut = 2.0 + c->near_gap;
+  // unit spheres: near when |c_t - c_s| - 2 < d*; radii a: when the gap
+  // |c_t - c_s| - a_t - a_s is below d* a_s (the source's own length scale)
+  const double cut = (2.0 + c->near_gap) * amax;
   const double cut2 = cut * cut;
   double lo[3] = {1e300, 1e300, 1e300};
   for (int64_t k = 0; k < nb; ++k)
@@ -277,9 +300,14 @@ void build(bie_ctx* c, const double* centres, int64_t nb, const bie_opts* o) {
             double ddy = centres[3 * k + 1] - centres[3 * s + 1];
             double ddz = centres[3 * k + 2] - centres[3 * s + 2];
             double d2 = ((ddx * ddx) + (ddy * ddy)) + (ddz * ddz);
-            if (d2 < 4.0)
+            const double rs = rad[k] + rad[s];
+            if (d2 < rs * rs)
               throw Error{BIE_EOVERLAP, "spheres " + std::to_string(k) + " and " + std::to_string(s) + " overlap"};
-            if (d2 < cut2) nbr[k].push_back(s);
+            if (!c->poly) {
+              if (d2 < cut2) nbr[k].push_back(s);
+            } else if (std::sqrt(d2) - rs < c->near_gap * rad[s]) {
+              nbr[k].push_back(s);
+            }
           }
         }
     std::sort(nbr[k].begin(), nbr[k].end());
@@ -378,6 +406,7 @@ void build(bie_ctx* c, const double* centres, int64_t nb, const bie_opts* o) {
     c4[4 * k + 3] = 0.0;
   }
   upload_vec(c->centres4, c4);
+  if (c->poly) upload_vec(c->radius_d, c->radius);
   upload_vec(c->excl, ex);
   upload_vec(c->dnear_ptr, c->near_ptr);
   upload_vec(c->dnear_idx, c->near_idx.empty() ? std::vector<int>{0} : c->near_idx);

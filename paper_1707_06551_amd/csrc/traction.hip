@@ -51,6 +51,7 @@ struct TracParams {
   const int* near_idx;
   const double* otab;      // P x 4 unit offsets (= outward normals) of the nodes
   const double* rec2;      // ncoef2 x 6 recurrence constants, degree <= p+1, m <= mm2
+  const double* radius;    // nb radii, or null for unit spheres
   double* u;
   int p, mmax, P, ncoef, p2, mm2, ncoef2;
 };
@@ -269,6 +270,9 @@ __global__ __launch_bounds__(256) void near_traction_kernel(TracParams a) {
     o[2] = a.otab[4 * g + 2];
   }
   const double* ctp = a.centres4 + 4 * t;
+  // spheres of radius a: the node is c_t + a_t o; the traction is scale invariant, so the
+  // series is evaluated at (x - c_s) / a_s with no further factor
+  const double at = a.radius ? a.radius[t] : 1.0;
   double acc[3] = {0.0, 0.0, 0.0};
   for (int e = s0; e < s1; ++e) {
     const int s = a.near_idx[e];
@@ -277,7 +281,13 @@ __global__ __launch_bounds__(256) void near_traction_kernel(TracParams a) {
     __syncthreads();
     if (!active) continue;
     const double* csp = a.centres4 + 4 * s;
-    const double d[3] = {(ctp[0] - csp[0]) + o[0], (ctp[1] - csp[1]) + o[1], (ctp[2] - csp[2]) + o[2]};
+    double d[3] = {(ctp[0] - csp[0]) + at * o[0], (ctp[1] - csp[1]) + at * o[1], (ctp[2] - csp[2]) + at * o[2]};
+    if (a.radius) {
+      const double ias = 1.0 / a.radius[s];
+      d[0] *= ias;
+      d[1] *= ias;
+      d[2] *= ias;
+    }
     double tv[3];
     traction_point(a, cs, rec, d, o, tv);
     acc[0] += tv[0];
@@ -324,6 +334,7 @@ void launch_near_traction(bie_ctx* c, double* u) {
   a.near_idx = c->dnear_idx.as<int>();
   a.otab = c->otab.as<double>();
   a.rec2 = c->rec2.as<double>();
+  a.radius = c->poly ? c->radius_d.as<double>() : nullptr;
   a.u = u;
   a.p = c->p;
   a.mmax = c->mmax;

@@ -34,6 +34,9 @@ struct VshParams {
   int accumulate;  // u += synthesis (else u = synthesis)
   double wv1;      // n = 1 coupling: V'_1 += wv1 * W_1 (preconditioner of the completed form)
   double lam[3][33];
+  const double* radius;  // per-sphere radii for lam_mode 1, 2 (see VshCall)
+  int lam_mode;
+  double lamS[3][33];
 };
 
 __device__ inline double wave_sum(double v) {
@@ -168,7 +171,19 @@ __global__ __launch_bounds__(256) void vsh_kernel(VshParams a) {
         co[(2 * nc + i) * 2 + 1] = xi;
       }
       if (a.do_self) {
-        const R lv = (R)a.lam[0][n], lw = (R)a.lam[1][n], lx = (R)a.lam[2][n];
+        R lv = (R)a.lam[0][n], lw = (R)a.lam[1][n], lx = (R)a.lam[2][n];
+        if (a.lam_mode != 0) {
+          // sphere of radius a_k: the single layer's eigenvalues scale with a_k
+          const double rad = a.radius[k];
+          double l3[3];
+          for (int f = 0; f < 3; ++f) {
+            const double s = rad * a.lamS[f][n] + a.lam[f][n];
+            l3[f] = (a.lam_mode == 1) ? s : (s != 0.0 ? 1.0 / s - 2.0 : 0.0);
+          }
+          lv = (R)l3[0];
+          lw = (R)l3[1];
+          lx = (R)l3[2];
+        }
         const R w0r = wr, w0i = wi;
         vr *= lv;
         vi *= lv;
@@ -366,6 +381,10 @@ void launch_vsh(bie_ctx* c, int precision, const VshCall& v) {
   a.wv1 = v.wv1;
   for (int f = 0; f < 3; ++f)
     for (int n = 0; n < 33; ++n) a.lam[f][n] = v.lam[f][n];
+  a.radius = v.radius;
+  a.lam_mode = v.radius ? v.lam_mode : 0;
+  for (int f = 0; f < 3; ++f)
+    for (int n = 0; n < 33; ++n) a.lamS[f][n] = v.lamS[f][n];
   const size_t sm = vsh_smem(c, f32 ? sizeof(float) : sizeof(double));
   if (f32)
     vsh_kernel<float><<<dim3((unsigned)c->nb), dim3(256), sm, c->stream>>>(a);

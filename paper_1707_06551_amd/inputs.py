@@ -126,3 +126,32 @@ def lattice_centres(units, q):
     g = np.arange(units + 1, dtype=np.float64) * h
     x, y, z = np.meshgrid(g, g, g, indexing="ij")
     return np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+
+
+def lattice_poly(units, q):
+    """The polydisperse lattice units of the scaling experiment (Section 6, Fig. 8 (c),
+    (d)) rescaled so that the vertex spheres are unit: vertex spheres of radius 1 on a
+    cubic grid of spacing 2 / (1 - 2^-q), one sphere of radius 2 - sqrt(2) at the centre
+    of every cube face and one of radius sqrt(2) - 1 at the centre of every cube.
+    Returns (centres (n, 3), radii (n,)); (units+1)^3 + 3 (units+1) units^2 + units^3
+    spheres (15, 71, 429, 2969, 22065 for 1, 2, 4, 8, 16 units).  With the printed radii a
+    face sphere overlaps its vertex spheres once (3 - sqrt(2)) (1 - 2^-q) > sqrt(2),
+    i.e. for q >= 4: those lattices are refused."""
+    rv = 1.0 - 2.0 ** (-q)
+    if (3.0 - math.sqrt(2.0)) * rv >= math.sqrt(2.0):
+        raise ValueError(f"q = {q}: face and vertex spheres of the printed radii overlap")
+    h = 2.0 / rv
+    v = lattice_centres(units, q)
+    g = np.arange(units + 1, dtype=np.float64) * h
+    m = (np.arange(units, dtype=np.float64) + 0.5) * h
+    faces = []
+    for axis in range(3):
+        a, b, c = np.meshgrid(g, m, m, indexing="ij")
+        f = np.stack([a.ravel(), b.ravel(), c.ravel()], axis=1)
+        faces.append(np.roll(f, axis, axis=1))
+    x, y, z = np.meshgrid(m, m, m, indexing="ij")
+    cen = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+    centres = np.concatenate([v] + faces + [cen], axis=0)
+    radii = np.concatenate([np.ones(len(v)), np.full(sum(len(f) for f in faces), 2.0 - math.sqrt(2.0)),
+                            np.full(len(cen), math.sqrt(2.0) - 1.0)])
+    return centres, radii

@@ -1,0 +1,176 @@
+"""GPU parity of the polydisperse operators (spheres of several radii: S, D, S + D, K and
+the porous-media solve) against the oracle with per-sphere radii (oracle/grid.py,
+oracle/operators.py, oracle/traction.py)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import traction as tr
+from oracle.grid import Geometry
+from oracle.operators import OPS as ORACLE_OPS, Operators
+from oracle.solvers import assemble
+from tests.gpu_common import max_rel, rel_err
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+OPS = {"S": 1, "D": 2, "SD_BIE": 3}
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).reshape(-1)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def poly_cluster():
+    """Six spheres of radii 0.35-1.4, gaps 0.12-0.9 among the near pairs."""
+    c = np.array([[0.0, 0.0, 0.0], [2.2, 0.3, -0.1], [0.4, 1.75, 0.5], [-1.5, -0.6, 0.9],
+                  [1.3, -1.4, 1.2], [4.4, 2.2, 0.4]])
+    a = np.array([1.0, 1.1, 0.45, 0.6, 0.35, 1.4])
+    return c, a
+
+
+@pytest.fixture(scope="module")
+def cluster():
+    from paper_1707_06551_amd import bie
+    c, a = poly_cluster()
+    p = 6
+    s = bie.Spheres(c, p, near_gap=1.0, radii=a)
+    g = Geometry(c, p, near_gap=1.0, radii=a)
+    yield c, a, s, g
+    s.close()
+
+
+def test_nodes_and_near_pairs(cluster):
+    c, a, s, g = cluster
+    xyz, w = s.nodes()
+    assert np.abs(xyz - g.nodes).max() < 1e-14 and np.abs(w - g.w).max() < 1e-15
+    pairs = s.near_pairs()
+    ref = sorted((t, q) for t in range(g.nb) for q in range(g.nb) if g.near[t, q])
+    assert sorted(map(tuple, pairs.T.tolist())) == ref
+    assert not np.array_equal(g.near, g.near.T)   # the radius-scaled test is directed
+
+
+@pytest.mark.parametrize("opname", ["S", "D", "SD_BIE"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_operators_match_oracle(cluster, opname, precision):
+    c, a, s, g = cluster
+    ops = Operators(g)
+    mu = np.random.default_rng(1).standard_normal((g.N, 3))
+    out = host(s.apply(OPS[opname], dev(mu), precision=precision)).reshape(g.N, 3)
+    ref = ops.apply(opname, mu)
+    tol = 1e-11 if precision == 0 else 1e-6
+    assert rel_err(out, ref) < tol, (rel_err(out, ref), max_rel(out, ref))
+
+
+@pytest.mark.parametrize("stage", ["self", "near", "far"])
+def test_stages_match_oracle(cluster, stage):
+    from paper_1707_06551_amd import bie
+    c, a, s, g = cluster
+    ops = Operators(g)
+    mu = np.random.default_rng(2).standard_normal((g.N, 3))
+    bits = {"self": bie.STAGE_SELF, "near": bie.STAGE_NEAR, "far": bie.STAGE_FAR}[stage]
+    out = host(s.apply(bie.OP_SD_BIE | bits, dev(mu))).reshape(g.N, 3)
+    if stage == "self":
+        ref = ops.self_part(mu, 1.0, 1.0) + 0.5 * mu
+    elif stage == "near":
+        ref = ops.near_part(mu, 1.0, 1.0)
+    else:
+        ref = ops.far_part(mu, 1.0, 1.0)
+    assert rel_err(out, ref) < 1e-11, (rel_err(out, ref), max_rel(out, ref))
+
+
+def test_traction_matches_oracle(cluster):
+    from paper_1707_06551_amd import bie
+    c, a, s, g = cluster
+    mu = np.random.default_rng(3).standard_normal((g.N, 3))
+    out = host(s.apply(bie.OP_K, dev(mu))).reshape(g.N, 3)
+    ref = tr.TractionOps(g).apply_K(mu)
+    assert rel_err(out, ref) < 1e-11, (rel_err(out, ref), max_rel(out, ref))
+
+
+def test_scaled_configuration(cluster):
+    # scaling all centres and radii by lam multiplies S by lam and leaves D, K unchanged
+    from paper_1707_06551_amd import bie
+    c, a, s, g = cluster
+    lam = 1.7
+    s2 = bie.Spheres(lam * c, g.p, near_gap=1.0, radii=lam * a)
+    mu = dev(np.random.default_rng(4).standard_normal(3 * g.N))
+    for op, f in ((bie.OP_S, lam), (bie.OP_D, 1.0), (bie.OP_K, 1.0)):
+        u1 = host(s.apply(op, mu))
+        u2 = host(s2.apply(op, mu))
+        assert rel_err(u2, f * u1) < 1e-12, op
+    s2.close()
+
+
+def test_unit_radii_take_the_monodisperse_path():
+    from paper_1707_06551_amd import bie
+    c, _a = poly_cluster()
+    s0 = bie.Spheres(1.5 * c, 5, near_gap=1.0)
+    s1 = bie.Spheres(1.5 * c, 5, near_gap=1.0, radii=np.ones(len(c)))
+    mu = dev(np.random.default_rng(5).standard_normal(3 * s0.N))
+    for op in (bie.OP_SD_BIE, bie.OP_DN_BIE):
+        assert np.array_equal(host(s0.apply(op, mu)), host(s1.apply(op, mu)))
+    s0.close()
+    s1.close()
+
+
+def test_m0_inverts_an_isolated_sphere_of_radius_a():
+    from paper_1707_06551_amd import bie
+    s = bie.Spheres(np.array([[0.2, 0.1, -0.3]]), 7, radii=[0.4])
+    mu = np.random.default_rng(6).standard_normal(3 * s.N)
+    z = host(s.apply_precond(bie.OP_SD_BIE, s.apply(bie.OP_SD_BIE, dev(mu)), precond=bie.PC_M0))
+    assert max_rel(z, mu) < 1e-12
+    s.close()
+
+
+def test_porous_media_solve_matches_oracle(cluster):
+    # Problem 1: spheres held fixed in a uniform stream U, (1/2 + S + D) mu = -U
+    from paper_1707_06551_amd import bie
+    c, a, s, g = cluster
+    U = np.array([0.3, -0.8, 0.5])
+    b = -np.tile(U, g.N)
+    x, info = s.solve(bie.OP_SD_BIE, dev(b), tol=1e-12, precond=bie.PC_M0)
+    assert info["converged"], info
+    ops = Operators(g)
+    A = assemble(lambda m: ops.apply("SD_BIE", m.reshape(g.N, 3, -1)).reshape(3 * g.N, -1), 3 * g.N)
+    mu = np.linalg.solve(A, b)
+    assert rel_err(host(x), mu) < 1e-9
+    x2, info2 = s.solve(bie.OP_SD_BIE, dev(b), tol=1e-10, precision=bie.MIXED, precond=bie.PC_M0)
+    assert info2["converged"] and rel_err(host(x2), mu) < 1e-8
+    print(f"polydisperse porous media, 6 spheres p = 6: GMRES {info['iters']} (M0), mixed {info2['iters']}")
+
+
+def test_fixed_sphere_of_radius_a_drag():
+    from paper_1707_06551_amd import bie
+    a = 0.3
+    s = bie.Spheres(np.array([[1.0, -2.0, 0.5]]), 8, radii=[a])
+    U = np.array([1.0, 0.5, -0.25])
+    x, info = s.solve(bie.OP_SD_BIE, dev(-np.tile(U, s.N)), tol=1e-13, precond=bie.PC_M0)
+    _xyz, w = s.nodes()
+    F = (host(x).reshape(-1, 3) * w[:, None]).sum(axis=0)
+    assert np.abs(F + 6 * math.pi * a * U).max() < 1e-11
+    s.close()
+
+
+def test_polydisperse_rejects_unit_only_features(cluster):
+    from paper_1707_06551_amd import bie
+    c, a, s, g = cluster
+    mu = dev(np.zeros(3 * g.N))
+    with pytest.raises(bie.BieError):
+        s.apply(bie.OP_DN_BIE, mu)
+    with pytest.raises(bie.BieError):
+        s.solve_mobility(np.zeros((g.nb, 3)), np.ones((g.nb, 3)))
+    with pytest.raises(bie.BieError):
+        s.solve_resistance(np.zeros((g.nb, 3)), np.ones((g.nb, 3)))
+    with pytest.raises(bie.BieError):
+        s.apply_precond(bie.OP_SD_BIE, mu, precond=bie.PC_MLP)
+    with pytest.raises(bie.BieError):
+        bie.Spheres(c, 4, radii=a, near_method=1)
+    with pytest.raises(bie.BieError):
+        bie.Spheres(c, 4, radii=np.full(len(a), 1.2))   # overlapping

@@ -1,0 +1,114 @@
+"""Pins of the polydisperse (per-sphere radius) oracle: scale invariance of the layer
+operators, the exterior series on a sphere of radius a against brute-force quadrature,
+the textbook flow past a fixed sphere of radius a, and unit radii reproducing the
+monodisperse operators."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import kernels
+from oracle import traction as tr
+from oracle.grid import Geometry, sphere_grid
+from oracle.harmonics import DenseVSH, vsh_at
+from oracle.operators import Operators
+from oracle.solvers import assemble
+
+
+def poly_cluster(seed=3):
+    """Six spheres of radii 0.35-1.4 with several near pairs (gaps 0.05-0.6)."""
+    c = np.array([[0.0, 0.0, 0.0], [2.2, 0.3, -0.1], [0.4, 1.75, 0.5], [-1.5, -0.6, 0.9],
+                  [1.3, -1.4, 1.2], [4.4, 2.2, 0.4]])
+    a = np.array([1.0, 1.1, 0.45, 0.6, 0.35, 1.4])
+    d = np.linalg.norm(c[:, None] - c[None, :], axis=-1) - a[:, None] - a[None, :]
+    np.fill_diagonal(d, np.inf)
+    assert d.min() > 0.04
+    return c, a
+
+
+def test_unit_radii_reproduce_the_monodisperse_operators():
+    c, _a = poly_cluster()
+    g0 = Geometry(c * 1.5, 5, near_gap=1.0)
+    g1 = Geometry(c * 1.5, 5, near_gap=1.0, radii=np.ones(len(c)))
+    mu = np.random.default_rng(1).standard_normal((g0.N, 3))
+    for op in ("S", "D", "SD_BIE", "DN_BIE"):
+        assert np.array_equal(Operators(g0).apply(op, mu), Operators(g1).apply(op, mu))
+    assert np.array_equal(g0.near, g1.near)
+
+
+@pytest.mark.parametrize("lam", [0.6, 1.7])
+def test_scale_invariance(lam):
+    # the single layer is homogeneous of degree 1 in the length scale, the double layer
+    # and the traction of degree 0: scaling every centre and radius by lam maps the
+    # same nodal density to lam * S, D, K (self, near and far parts together)
+    c, a = poly_cluster()
+    p = 5
+    g = Geometry(c, p, near_gap=1.0, radii=a)
+    gs = Geometry(lam * c, p, near_gap=1.0, radii=lam * a)
+    assert np.array_equal(g.near, gs.near) and g.near.sum() > 0
+    mu = np.random.default_rng(2).standard_normal((g.N, 3))
+    o, os_ = Operators(g), Operators(gs)
+    S, Ss = o.apply("S", mu), os_.apply("S", mu)
+    D, Ds = o.apply("D", mu), os_.apply("D", mu)
+    K, Ks = tr.TractionOps(g).apply_K(mu), tr.TractionOps(gs).apply_K(mu)
+    assert np.abs(Ss - lam * S).max() < 1e-12 * np.abs(S).max() * 10
+    assert np.abs(Ds - D).max() < 1e-12 * np.abs(D).max() * 10
+    assert np.abs(Ks - K).max() < 1e-12 * np.abs(K).max() * 10
+
+
+@pytest.mark.parametrize("radius", [0.4, 1.6])
+def test_exterior_series_on_a_sphere_of_radius_a_matches_quadrature(radius):
+    # band-limited density on a sphere of radius a, points 0.6 a - 2 a from its surface;
+    # brute force on a fine grid of the same sphere (nodes a xhat, weights a^2 w)
+    p = 5
+    g = Geometry(np.zeros((1, 3)), p, n_phi=2 * p + 2)
+    ops = Operators(g)
+    rng = np.random.default_rng(3)
+    mu = rng.standard_normal((g.P, 3))
+    coef = DenseVSH(g.grid, p, g.mmax).forward(mu)[..., None]
+    fine = sphere_grid(40, 82)
+    _m, _Y, V, W, X = vsh_at(fine["xhat"], p, g.mmax)
+    dens = (np.einsum("mki,m->ki", V, coef[0, :, 0]) + np.einsum("mki,m->ki", W, coef[1, :, 0])
+            + np.einsum("mki,m->ki", X, coef[2, :, 0])).real
+    d = rng.standard_normal((6, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    x = radius * (1.6 + 1.4 * rng.random(6))[:, None] * d
+    q = (dens * (radius ** 2 * fine["wnode"])[:, None])[:, :, None]
+    for a_s, a_d in ((1.0, 0.0), (0.0, 1.0), (1.0, 1.0)):
+        series = ops.near_field_from(coef, np.zeros(3), x, a_s, a_d, radius)[..., 0]
+        brute = kernels.direct_sum(x, radius * fine["xhat"], fine["xhat"], q, a_s, a_d)[..., 0]
+        assert np.abs(series - brute).max() < 1e-11 * np.abs(brute).max(), (a_s, a_d)
+
+
+def test_fixed_sphere_of_radius_a_in_a_uniform_stream():
+    # Problem 1 on one sphere of radius a: the flow is the textbook one with a in place
+    # of 1, and the sphere exerts -6 pi a U on the fluid (int mu over the surface)
+    a = 0.45
+    cen = np.array([0.3, -0.2, 0.5])
+    g = Geometry(cen[None, :], 10, near_gap=1.0, radii=[a])
+    ops = Operators(g)
+    U = np.array([0.4, -1.1, 0.7])
+    A = assemble(lambda m: ops.apply("SD_BIE", m.reshape(g.N, 3, -1)).reshape(3 * g.N, -1), 3 * g.N)
+    mu = np.linalg.solve(A, -np.tile(U, g.N)).reshape(g.N, 3)
+    F = (mu * g.w[:, None]).sum(axis=0)
+    assert np.abs(F + 6 * math.pi * a * U).max() < 1e-11
+    rng = np.random.default_rng(4)
+    d = rng.standard_normal((5, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    x = cen[None, :] + a * np.array([1.05, 1.4, 2.5, 4.0, 9.0])[:, None] * d
+    coef = ops.coefficients(mu, 0)[..., None]
+    u = U[None, :] + ops.near_field_from(coef, cen, x, 1.0, 1.0, a)[..., 0]
+    r = x - cen[None, :]
+    dd = np.linalg.norm(r, axis=1)[:, None]
+    rU = (r @ U)[:, None]
+    ref = U[None, :] - 0.75 * a * (U[None, :] / dd + rU * r / dd ** 3) - 0.25 * a ** 3 * (U[None, :] / dd ** 3
+                                                                                          - 3 * rU * r / dd ** 5)
+    assert np.abs(u - ref).max() < 1e-12
+
+
+def test_near_classification_scales_with_the_source_radius():
+    # gap 0.3 between a unit sphere and a sphere of radius 0.2: within d* = 1 of the
+    # large source, beyond d* a_s = 0.2 of the small one
+    c = np.array([[0.0, 0.0, 0.0], [1.5, 0.0, 0.0]])
+    g = Geometry(c, 4, near_gap=1.0, radii=[1.0, 0.2])
+    assert g.near[1, 0] and not g.near[0, 1]
