@@ -140,15 +140,14 @@ class Operators:
         return out if batch else out[..., 0]
 
     def moments(self, mu):
-        """Per sphere: F_k = sum w mu, T_k = sum w (y - c_k) x mu  (quadrature, Eq. 4.4).
-        Returns (nb, 3, B), (nb, 3, B).  Unit spheres."""
+        """Per sphere: F_k = sum w mu, T_k = sum w (y - c_k) x mu  (quadrature, Eq. 4.4,
+        with the actual nodes and weights, so a sphere of radius a carries a^2 and a^3).
+        Returns (nb, 3, B), (nb, 3, B)."""
         mu, _ = self._as_batch(mu)
         g = self.g
-        if not g.unit:
-            raise NotImplementedError("moments, completion and bordered rows are for unit spheres")
         wm = mu * g.w[:, None, None]
         F = wm.reshape(g.nb, g.P, 3, -1).sum(axis=1)
-        o = g.xhat[:, :, None]
+        o = (g.nodes - g.centres[g.sphere_of])[:, :, None]
         Tq = np.stack([o[:, 1] * wm[:, 2] - o[:, 2] * wm[:, 1],
                        o[:, 2] * wm[:, 0] - o[:, 0] * wm[:, 2],
                        o[:, 0] * wm[:, 1] - o[:, 1] * wm[:, 0]], axis=1)
@@ -189,8 +188,10 @@ class Operators:
     def apply_mobility(self, xvec):
         """xvec = [mu (N*3); v (nb*3); omega (nb*3)] (flattened, [, B]) ->
         [1/2 mu + sum (S+D) mu - v_i - omega_i x (x - c_i);
-         (1/4pi) sum_k w mu;  (3/8pi) sum_k w (y - c_k) x mu]."""
+         (1/4pi) sum_k w mu;  (3/8pi) sum_k w (y - c_k) x mu].  Unit spheres."""
         g = self.g
+        if not g.unit:
+            raise NotImplementedError("the bordered mobility rows are written for unit spheres")
         xvec = np.asarray(xvec, dtype=np.float64)
         batch = xvec.ndim == 2
         if not batch:

@@ -8,6 +8,9 @@ the completion flow N maps W_1[b] -> 2/3 W_1[b] - 1/6 V_1[b] and X_1 -> 1/3 X_1;
 grid complement of the band-limited space the operator is 1/2.  Hence
     M0 r = 2 r + Pi^+ (L - 2) Pi r,   L = 1/D_+ per mode except
     V_1: 5/3 (plus 5/12 of the W_1 coefficient), W_1: 3/2, X_1: 3.
+On a sphere of radius a the completion's moments carry a^2 (force) and a^3 (torque) and
+are felt at distance a, so N maps W_1 -> 2a/3 W_1 - a/6 V_1 and X_1 -> a/3 X_1: W_1 and
+X_1 become 3/(2a) and 3/a, the V_1 coupling stays 5/12.
 
 Parity: pinned by tests/test_oracle_coarse.py (M0 inverts the isolated operator).
 """
@@ -31,7 +34,10 @@ def m0_resistance(geom, r):
     for k in range(geom.nb):
         sl = geom.sphere_nodes(k)
         c = vsh.forward(r[sl])
-        d = (lam - 2.0) * c
+        lk = lam.copy()
+        lk[1, i1] /= geom.radii[k]
+        lk[2, i1] /= geom.radii[k]
+        d = (lk - 2.0) * c
         d[0, i1] += (5.0 / 12.0) * c[1, i1]
         out[sl] = 2.0 * r[sl] + vsh.inverse(d)
     return out

@@ -97,7 +97,7 @@ def gmres(apply_fn, b, tol=1e-10, restart=100, max_iter=1000):
 def rigid_rhs(geom, v, omega):
     """v_i + omega_i x (x - c_i) at every node (N, 3)."""
     k = geom.sphere_of
-    return v[k] + np.cross(omega[k], geom.xhat)
+    return v[k] + np.cross(omega[k], geom.nodes - geom.centres[k])
 
 
 def solve_resistance(geom, v, omega, method="gmres", tol=1e-10, restart=100, max_iter=1000):

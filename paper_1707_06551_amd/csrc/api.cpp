@@ -49,8 +49,8 @@ void apply(bie_ctx* c, int op, int precision, const double* mu, double* u) {
   const OpSpec spec = op_spec(base);
   if (spec.traction && c->near_method != 0)
     throw Error{BIE_EINVAL, "the traction operator supports near_method 0 (series at the target nodes) only"};
-  if (c->poly && (spec.completion || spec.bordered || spec.rigid_local))
-    throw Error{BIE_EINVAL, "spheres of several radii support BIE_OP_S, _D, _SD_BIE and _K only"};
+  if (c->poly && (spec.bordered || spec.rigid_local))
+    throw Error{BIE_EINVAL, "spheres of several radii support BIE_OP_S, _D, _SD_BIE, _DN_BIE and _K only"};
   VshCall v;
   v.mu = mu;
   v.u = u;
@@ -102,9 +102,38 @@ void dev_precond_m0(bie_ctx* c, int op_base, int precision, const double* r, dou
   v.u = z;
   v.do_self = true;
   v.c_identity = 2.0;
+  if (c->poly && op_base == BIE_OP_DN_BIE) {
+    // completed form on a sphere of radius a: the completion's moments carry a^2 and a^3
+    // at distance a, so W_1 -> 3/(2a) and X_1 -> 3/a; V_1 (5/3, coupling 5/12) and the
+    // other modes (1/D_+) do not depend on a
+    for (int n = 0; n <= c->p; ++n) {
+      double ed[3];
+      eig_Dplus(n, ed);
+      for (int f = 0; f < 3; ++f) {
+        const bool exists = (f == 0) || n >= 1;
+        v.lamS[f][n] = 0.0;
+        if (!exists) {
+          v.lam[f][n] = 0.0;
+        } else if (n == 1 && f == 0) {
+          v.lam[f][n] = 5.0 / 3.0 - 2.0;
+        } else if (n == 1) {
+          v.lamS[f][n] = (f == 1) ? 1.5 : 3.0;
+          v.lam[f][n] = -2.0;
+        } else {
+          v.lam[f][n] = 1.0 / ed[f] - 2.0;
+        }
+      }
+    }
+    v.wv1 = 5.0 / 12.0;
+    v.radius = c->radius_d.as<double>();
+    v.lam_mode = 3;
+    launch_vsh(c, precision, v);
+    return;
+  }
   if (c->poly) {
-    // spheres of radius a_k, 1/2 + S + D_pv only: 1 / (a_k lambda_S + lambda_D+) per mode
-    if (op_base != BIE_OP_SD_BIE) throw Error{BIE_EINVAL, "spheres of several radii: M0 exists for BIE_OP_SD_BIE"};
+    // spheres of radius a_k, 1/2 + S + D_pv: 1 / (a_k lambda_S + lambda_D+) per mode
+    if (op_base != BIE_OP_SD_BIE)
+      throw Error{BIE_EINVAL, "spheres of several radii: M0 exists for BIE_OP_SD_BIE and BIE_OP_DN_BIE"};
     for (int n = 0; n <= c->p; ++n) {
       double es[3], ed[3];
       eig_S(n, es);
@@ -166,8 +195,9 @@ void apply_precond(bie_ctx* c, int op_base, int precision, int precond, const do
   const int64_t n = 3 * c->N + (op_base == BIE_OP_MOBILITY ? 6 * c->nb : 0);
   const bool rigid = (precond & BIE_PC_RIGID) != 0;
   const int base = precond & ~BIE_PC_RIGID;
-  if (c->poly && (op_base != BIE_OP_SD_BIE || (precond & ~BIE_PC_M0) != 0))
-    throw Error{BIE_EINVAL, "spheres of several radii: preconditioners BIE_PC_NONE / BIE_PC_M0 of BIE_OP_SD_BIE only"};
+  if (c->poly && ((op_base != BIE_OP_SD_BIE && op_base != BIE_OP_DN_BIE) || (precond & ~BIE_PC_M0) != 0))
+    throw Error{BIE_EINVAL,
+                "spheres of several radii: preconditioners BIE_PC_NONE / BIE_PC_M0 of BIE_OP_SD_BIE, BIE_OP_DN_BIE only"};
   if (rigid && base == BIE_PC_NONE) throw Error{BIE_EINVAL, "BIE_PC_RIGID needs BIE_PC_M0 or BIE_PC_MLP"};
   if (rigid && c->nb > RIGID_MAX_SPHERES) throw Error{BIE_EINVAL, "BIE_PC_RIGID: too many spheres for the coarse solve"};
   switch (base) {
@@ -344,14 +374,17 @@ int bie_solve_resistance(bie_ctx* c, const double* v, const double* omega, const
   }
   int rc = BIE_OK;
   BIE_TRY({
-    bie::require_unit(c, "bie_solve_resistance");
     const int64_t n = 3 * c->N;
     bie::DevBuf rhs, x, vw;
     rhs.alloc(n * sizeof(double));
     x.alloc(n * sizeof(double));
     vw.alloc(6 * c->nb * sizeof(double));
+    // omega_i x (x - c_i) with x - c_i = a_i o: the unit-offset kernel takes a_i omega_i
+    std::vector<double> om(omega, omega + 3 * c->nb);
+    for (int64_t k = 0; k < c->nb; ++k)
+      for (int d = 0; d < 3; ++d) om[3 * k + d] *= c->radius[k];
     BIE_HIP(hipMemcpyAsync(vw.ptr, v, 3 * c->nb * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    BIE_HIP(hipMemcpyAsync(vw.as<double>() + 3 * c->nb, omega, 3 * c->nb * sizeof(double), hipMemcpyHostToDevice,
+    BIE_HIP(hipMemcpyAsync(vw.as<double>() + 3 * c->nb, om.data(), 3 * c->nb * sizeof(double), hipMemcpyHostToDevice,
                            c->stream));
     bie::dev_rigid_rhs(c, vw.as<double>(), vw.as<double>() + 3 * c->nb, rhs.as<double>());
     rc = bie::solve(c, BIE_OP_DN_BIE, rhs.as<double>(), x.as<double>(), n, opts, info);
@@ -359,6 +392,10 @@ int bie_solve_resistance(bie_ctx* c, const double* v, const double* omega, const
     bie::VshCall m;
     m.mu = x.as<double>();
     m.want_moments = true;
+    if (c->poly) {
+      m.radius = c->radius_d.as<double>();
+      m.lam_mode = 1;
+    }
     bie::launch_vsh(c, BIE_FP64, m);
     std::vector<double> mom(6 * c->nb);
     BIE_HIP(hipMemcpyAsync(mom.data(), c->moments.ptr, mom.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));

@@ -145,7 +145,8 @@ struct VshCall {
   double lam[3][33] = {};
   // per-sphere multipliers for spheres of radius a_k (radius != nullptr):
   //   lam_mode 1: a_k lamS + lam (operator);  2: 1 / (a_k lamS + lam) - 2 (M0), 0 where
-  //   both vanish
+  //   both vanish;  3: lamS / a_k + lam (M0 of the completed form).  With radius set the
+  //   moments carry a_k^2 (force) and a_k^3 (torque)
   const double* radius = nullptr;
   int lam_mode = 0;
   double lamS[3][33] = {};

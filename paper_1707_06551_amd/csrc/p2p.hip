@@ -198,7 +198,8 @@ __global__ __launch_bounds__(256) void far_kernel(FarParams a) {
       any = any || !skip[k];
       if (a.completion && valid[k]) {
         // Stokeslet of strength F_s and rotlet of torque T_s at c_s, in float64
-        const double qx = dx + (double)oxt[k][0], qy = dy + (double)oxt[k][1], qz = dz + (double)oxt[k][2];
+        const double qx = dx + at[k] * (double)oxt[k][0], qy = dy + at[k] * (double)oxt[k][1],
+                     qz = dz + at[k] * (double)oxt[k][2];
         const double* mo = a.moments + 6 * (int64_t)s;
         const double r2 = qx * qx + qy * qy + qz * qz;
         const double ir = rsqrt_r<double>(r2);   // refined estimate: 1.0-1.3% faster than 1/sqrt (measured)

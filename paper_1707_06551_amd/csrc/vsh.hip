@@ -103,6 +103,11 @@ __global__ __launch_bounds__(256) void vsh_kernel(VshParams a) {
       if (tid < 6) {
         double s = 0.0;
         for (int w = 0; w < nw; ++w) s += red[tid * 4 + w];
+        if (a.radius) {
+          // sphere of radius a: area element a^2, lever arm a
+          const double rad = a.radius[k];
+          s *= (tid < 3) ? rad * rad : rad * rad * rad;
+        }
         a.moments[6 * k + tid] = s;
         red[32 + tid] = s;
       }
@@ -177,8 +182,12 @@ __global__ __launch_bounds__(256) void vsh_kernel(VshParams a) {
           const double rad = a.radius[k];
           double l3[3];
           for (int f = 0; f < 3; ++f) {
-            const double s = rad * a.lamS[f][n] + a.lam[f][n];
-            l3[f] = (a.lam_mode == 1) ? s : (s != 0.0 ? 1.0 / s - 2.0 : 0.0);
+            if (a.lam_mode == 3) {
+              l3[f] = a.lamS[f][n] / rad + a.lam[f][n];
+            } else {
+              const double s = rad * a.lamS[f][n] + a.lam[f][n];
+              l3[f] = (a.lam_mode == 1) ? s : (s != 0.0 ? 1.0 / s - 2.0 : 0.0);
+            }
           }
           lv = (R)l3[0];
           lw = (R)l3[1];

@@ -15,7 +15,7 @@ from tests.gpu_common import max_rel, rel_err
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-OPS = {"S": 1, "D": 2, "SD_BIE": 3}
+OPS = {"S": 1, "D": 2, "SD_BIE": 3, "DN_BIE": 4}
 
 
 def dev(a):
@@ -56,7 +56,7 @@ def test_nodes_and_near_pairs(cluster):
     assert not np.array_equal(g.near, g.near.T)   # the radius-scaled test is directed
 
 
-@pytest.mark.parametrize("opname", ["S", "D", "SD_BIE"])
+@pytest.mark.parametrize("opname", ["S", "D", "SD_BIE", "DN_BIE"])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_operators_match_oracle(cluster, opname, precision):
     c, a, s, g = cluster
@@ -120,13 +120,46 @@ def test_unit_radii_take_the_monodisperse_path():
     s1.close()
 
 
-def test_m0_inverts_an_isolated_sphere_of_radius_a():
+@pytest.mark.parametrize("op", [3, 4])
+def test_m0_inverts_an_isolated_sphere_of_radius_a(op):
     from paper_1707_06551_amd import bie
-    s = bie.Spheres(np.array([[0.2, 0.1, -0.3]]), 7, radii=[0.4])
-    mu = np.random.default_rng(6).standard_normal(3 * s.N)
-    z = host(s.apply_precond(bie.OP_SD_BIE, s.apply(bie.OP_SD_BIE, dev(mu)), precond=bie.PC_M0))
-    assert max_rel(z, mu) < 1e-12
+    for a in (0.4, 2.5):
+        s = bie.Spheres(np.array([[0.2, 0.1, -0.3]]), 7, radii=[a])
+        mu = np.random.default_rng(6).standard_normal(3 * s.N)
+        z = host(s.apply_precond(op, s.apply(op, dev(mu)), precond=bie.PC_M0))
+        assert max_rel(z, mu) < 1e-12, a
+        s.close()
+
+
+def test_resistance_of_an_isolated_sphere_of_radius_a():
+    # Problem 5: F = 6 pi a v, T = 8 pi a^3 omega
+    from paper_1707_06551_amd import bie
+    a = 0.45
+    s = bie.Spheres(np.array([[0.5, 0.2, -1.0]]), 6, radii=[a])
+    v = np.array([[0.3, -1.0, 0.8]])
+    om = np.array([[1.1, 0.2, -0.5]])
+    F, T, _psi, info = s.solve_resistance(v, om, tol=1e-13, precond=bie.PC_M0)
+    assert info["converged"], info
+    assert np.abs(F - 6 * math.pi * a * v).max() < 1e-11
+    assert np.abs(T - 8 * math.pi * a ** 3 * om).max() < 1e-11
     s.close()
+
+
+def test_resistance_matches_oracle(cluster):
+    from oracle import solvers
+    from paper_1707_06551_amd import bie
+    c, a, s, g = cluster
+    rng = np.random.default_rng(8)
+    v = rng.standard_normal((g.nb, 3))
+    om = rng.standard_normal((g.nb, 3))
+    F, T, psi, info = s.solve_resistance(v, om, tol=1e-12, precond=bie.PC_M0, want_psi=True)
+    assert info["converged"], info
+    F_o, T_o, psi_o, _i = solvers.solve_resistance(g, v, om, method="lu")
+    assert rel_err(F, F_o) < 1e-9 and rel_err(T, T_o) < 1e-9, (rel_err(F, F_o), rel_err(T, T_o))
+    assert rel_err(host(psi).reshape(g.N, 3), psi_o) < 1e-8
+    F2, T2, _p, info2 = s.solve_resistance(v, om, tol=1e-10, precision=bie.MIXED, precond=bie.PC_M0)
+    assert info2["converged"] and rel_err(F2, F_o) < 1e-8 and rel_err(T2, T_o) < 1e-8
+    print(f"polydisperse resistance, 6 spheres p = 6: GMRES {info['iters']} (M0), mixed {info2['iters']}")
 
 
 def test_porous_media_solve_matches_oracle(cluster):
@@ -163,11 +196,11 @@ def test_polydisperse_rejects_unit_only_features(cluster):
     c, a, s, g = cluster
     mu = dev(np.zeros(3 * g.N))
     with pytest.raises(bie.BieError):
-        s.apply(bie.OP_DN_BIE, mu)
+        s.apply(bie.OP_MOBILITY, dev(np.zeros(3 * g.N + 6 * g.nb)))
     with pytest.raises(bie.BieError):
         s.solve_mobility(np.zeros((g.nb, 3)), np.ones((g.nb, 3)))
     with pytest.raises(bie.BieError):
-        s.solve_resistance(np.zeros((g.nb, 3)), np.ones((g.nb, 3)))
+        s.solve_resistance(np.zeros((g.nb, 3)), np.ones((g.nb, 3)), precond=bie.PC_M0 | bie.PC_RIGID)
     with pytest.raises(bie.BieError):
         s.apply_precond(bie.OP_SD_BIE, mu, precond=bie.PC_MLP)
     with pytest.raises(bie.BieError):

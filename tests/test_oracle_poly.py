@@ -112,3 +112,43 @@ def test_near_classification_scales_with_the_source_radius():
     c = np.array([[0.0, 0.0, 0.0], [1.5, 0.0, 0.0]])
     g = Geometry(c, 4, near_gap=1.0, radii=[1.0, 0.2])
     assert g.near[1, 0] and not g.near[0, 1]
+
+
+def test_isolated_sphere_of_radius_a_resistance():
+    # Problem 5 on one sphere of radius a: F = 6 pi a v, T = 8 pi a^3 omega (Stokes)
+    from oracle import solvers
+    a = 0.6
+    g = Geometry(np.array([[0.2, 0.4, -0.1]]), 6, radii=[a])
+    v = np.array([[0.3, -1.0, 0.8]])
+    om = np.array([[1.1, 0.2, -0.5]])
+    F, T, _psi, info = solvers.solve_resistance(g, v, om, method="lu")
+    assert np.abs(F - 6 * math.pi * a * v).max() < 1e-11
+    assert np.abs(T - 8 * math.pi * a ** 3 * om).max() < 1e-11
+
+
+def test_m0_inverts_the_isolated_completed_operator_of_radius_a():
+    from oracle.precond import m0_resistance
+    for a in (0.3, 1.0, 2.5):
+        g = Geometry(np.zeros((1, 3)), 6, radii=[a])
+        r = np.random.default_rng(5).standard_normal((g.N, 3))
+        z = m0_resistance(g, Operators(g).apply("DN_BIE", r))
+        assert np.abs(z - r).max() < 1e-11 * np.abs(r).max(), a
+
+
+def test_resistance_scales_with_the_configuration():
+    # scaling centres and radii by lam, a pure translation gives lam F and lam^2 T.  In
+    # the completed form this holds because the rigid part of psi scales by 1/lam and the
+    # rest not at all, which needs the double layer of a rigid density to vanish off its
+    # sphere: exact for the operator, up to the far quadrature's error on the grid (p = 4
+    # here: ~5e-5 relative)
+    from oracle import solvers
+    c, a = poly_cluster()
+    lam = 1.4
+    rng = np.random.default_rng(6)
+    v = rng.standard_normal((len(c), 3))
+    zero = np.zeros_like(v)
+    g, gs = Geometry(c, 4, radii=a), Geometry(lam * c, 4, radii=lam * a)
+    F1, T1, _p, _i = solvers.solve_resistance(g, v, zero, tol=1e-12)
+    F2, T2, _p, _i = solvers.solve_resistance(gs, v, zero, tol=1e-12)
+    assert np.abs(F2 - lam * F1).max() < 1e-3 * np.abs(F1).max()
+    assert np.abs(T2 - lam ** 2 * T1).max() < 1e-3 * np.abs(T1).max()
