@@ -188,10 +188,8 @@ class Operators:
     def apply_mobility(self, xvec):
         """xvec = [mu (N*3); v (nb*3); omega (nb*3)] (flattened, [, B]) ->
         [1/2 mu + sum (S+D) mu - v_i - omega_i x (x - c_i);
-         (1/4pi) sum_k w mu;  (3/8pi) sum_k w (y - c_k) x mu].  Unit spheres."""
+         (1/4pi) sum_k w mu;  (3/8pi) sum_k w (y - c_k) x mu]."""
         g = self.g
-        if not g.unit:
-            raise NotImplementedError("the bordered mobility rows are written for unit spheres")
         xvec = np.asarray(xvec, dtype=np.float64)
         batch = xvec.ndim == 2
         if not batch:
@@ -202,7 +200,7 @@ class Operators:
         om = xvec[3 * g.N + 3 * g.nb:].reshape(g.nb, 3, B)
         u = self.apply("SD_BIE", mu)
         k = g.sphere_of
-        o = g.xhat[:, :, None]
+        o = (g.nodes - g.centres[k])[:, :, None]                  # x - c_k
         w_ = om[k]
         rot = np.stack([w_[:, 1] * o[:, 2] - w_[:, 2] * o[:, 1],
                         w_[:, 2] * o[:, 0] - w_[:, 0] * o[:, 2],

@@ -49,8 +49,8 @@ void apply(bie_ctx* c, int op, int precision, const double* mu, double* u) {
   const OpSpec spec = op_spec(base);
   if (spec.traction && c->near_method != 0)
     throw Error{BIE_EINVAL, "the traction operator supports near_method 0 (series at the target nodes) only"};
-  if (c->poly && (spec.bordered || spec.rigid_local))
-    throw Error{BIE_EINVAL, "spheres of several radii support BIE_OP_S, _D, _SD_BIE, _DN_BIE and _K only"};
+  if (c->poly && spec.rigid_local)
+    throw Error{BIE_EINVAL, "spheres of several radii: BIE_OP_KL_BIE is built for unit spheres only"};
   VshCall v;
   v.mu = mu;
   v.u = u;
@@ -131,9 +131,11 @@ void dev_precond_m0(bie_ctx* c, int op_base, int precision, const double* r, dou
     return;
   }
   if (c->poly) {
-    // spheres of radius a_k, 1/2 + S + D_pv: 1 / (a_k lambda_S + lambda_D+) per mode
-    if (op_base != BIE_OP_SD_BIE)
-      throw Error{BIE_EINVAL, "spheres of several radii: M0 exists for BIE_OP_SD_BIE and BIE_OP_DN_BIE"};
+    // spheres of radius a_k, 1/2 + S + D_pv: 1 / (a_k lambda_S + lambda_D+) per mode (and,
+    // for the bordered form, the closed-form rigid rows of the transform kernel)
+    if (op_base != BIE_OP_SD_BIE && op_base != BIE_OP_MOBILITY)
+      throw Error{BIE_EINVAL, "spheres of several radii: M0 exists for BIE_OP_SD_BIE, _DN_BIE and _MOBILITY"};
+    if (op_base == BIE_OP_MOBILITY) v.pc_border = true;
     for (int n = 0; n <= c->p; ++n) {
       double es[3], ed[3];
       eig_S(n, es);
@@ -195,9 +197,9 @@ void apply_precond(bie_ctx* c, int op_base, int precision, int precond, const do
   const int64_t n = 3 * c->N + (op_base == BIE_OP_MOBILITY ? 6 * c->nb : 0);
   const bool rigid = (precond & BIE_PC_RIGID) != 0;
   const int base = precond & ~BIE_PC_RIGID;
-  if (c->poly && ((op_base != BIE_OP_SD_BIE && op_base != BIE_OP_DN_BIE) || (precond & ~BIE_PC_M0) != 0))
-    throw Error{BIE_EINVAL,
-                "spheres of several radii: preconditioners BIE_PC_NONE / BIE_PC_M0 of BIE_OP_SD_BIE, BIE_OP_DN_BIE only"};
+  if (c->poly && (op_base == BIE_OP_KL_BIE || (precond & ~BIE_PC_M0) != 0))
+    throw Error{BIE_EINVAL, "spheres of several radii: preconditioners BIE_PC_NONE / BIE_PC_M0 of "
+                            "BIE_OP_SD_BIE, BIE_OP_DN_BIE and BIE_OP_MOBILITY only"};
   if (rigid && base == BIE_PC_NONE) throw Error{BIE_EINVAL, "BIE_PC_RIGID needs BIE_PC_M0 or BIE_PC_MLP"};
   if (rigid && c->nb > RIGID_MAX_SPHERES) throw Error{BIE_EINVAL, "BIE_PC_RIGID: too many spheres for the coarse solve"};
   switch (base) {
@@ -421,7 +423,6 @@ int bie_solve_mobility(bie_ctx* c, const double* F, const double* T, const doubl
   }
   int rc = BIE_OK;
   BIE_TRY({
-    bie::require_unit(c, "bie_solve_mobility");
     const int64_t n3 = 3 * c->N, n = n3 + 6 * c->nb;
     bie::DevBuf rhs, x;
     rhs.alloc(n * sizeof(double));

@@ -288,15 +288,20 @@ __global__ __launch_bounds__(256) void vsh_kernel(VshParams a) {
   // meets the force / torque rows r_F, r_T is
   //   v = (4 pi r_F - 3/2 int r_u) / (6 pi),  w = (8pi/3 r_T - 3 int o x r_u) / (8 pi),
   // and the density is A^-1 r_u + 3/2 v + 3 w x o.
+  // On a sphere of radius a (moments then carry a^2, a^3): A^-1 is 3/(2a) on W_1 and 3/a
+  // on X_1, so v = (4 pi r_F - 3/(2a) int r_u) / (6 pi a), w = (8pi/3 r_T - 3/a int (y - c)
+  // x r_u) / (8 pi a^3), and the density gains 3/(2a) v + 3 w x o.
+  const double rad = a.radius ? a.radius[k] : 1.0;
   double pv[3] = {0, 0, 0}, pw[3] = {0, 0, 0};
   if (a.pc_border) {
     const double* rF = a.mu + 3 * a.N + 3 * (int64_t)k;
     const double* rT = a.mu + 3 * a.N + 3 * a.nb + 3 * (int64_t)k;
     for (int d = 0; d < 3; ++d) {
-      pv[d] = (4.0 * M_PI * rF[d] - 1.5 * red[32 + d]) / (6.0 * M_PI);
-      pw[d] = ((8.0 * M_PI / 3.0) * rT[d] - 3.0 * red[35 + d]) / (8.0 * M_PI);
+      pv[d] = (4.0 * M_PI * rF[d] - (1.5 / rad) * red[32 + d]) / (6.0 * M_PI * rad);
+      pw[d] = ((8.0 * M_PI / 3.0) * rT[d] - (3.0 / rad) * red[35 + d]) / (8.0 * M_PI * rad * rad * rad);
     }
   }
+  const double pv_scale = 1.5 / rad;
   for (int g = tid; g < P; g += nt) {
     const int j = g / nphi, l = g - j * nphi;
     R f[3];
@@ -320,15 +325,16 @@ __global__ __launch_bounds__(256) void vsh_kernel(VshParams a) {
       for (int d = 0; d < 3; ++d) out[d] += a.c_identity * m3[d];
     }
     if (vk) {
-      // - v_k - omega_k x (x - c_k), x - c_k = e_r
-      out[0] -= vk[0] + (ok[1] * fr[2] - ok[2] * fr[1]);
-      out[1] -= vk[1] + (ok[2] * fr[0] - ok[0] * fr[2]);
-      out[2] -= vk[2] + (ok[0] * fr[1] - ok[1] * fr[0]);
+      // - v_k - omega_k x (x - c_k), x - c_k = a e_r
+      const double w0 = rad * ok[0], w1 = rad * ok[1], w2 = rad * ok[2];
+      out[0] -= vk[0] + (w1 * fr[2] - w2 * fr[1]);
+      out[1] -= vk[1] + (w2 * fr[0] - w0 * fr[2]);
+      out[2] -= vk[2] + (w0 * fr[1] - w1 * fr[0]);
     }
     if (a.pc_border) {
-      out[0] += 1.5 * pv[0] + 3.0 * (pw[1] * fr[2] - pw[2] * fr[1]);
-      out[1] += 1.5 * pv[1] + 3.0 * (pw[2] * fr[0] - pw[0] * fr[2]);
-      out[2] += 1.5 * pv[2] + 3.0 * (pw[0] * fr[1] - pw[1] * fr[0]);
+      out[0] += pv_scale * pv[0] + 3.0 * (pw[1] * fr[2] - pw[2] * fr[1]);
+      out[1] += pv_scale * pv[1] + 3.0 * (pw[2] * fr[0] - pw[0] * fr[2]);
+      out[2] += pv_scale * pv[2] + 3.0 * (pw[0] * fr[1] - pw[1] * fr[0]);
     }
     for (int d = 0; d < 3; ++d) a.u[3 * (base + g) + d] = a.accumulate ? a.u[3 * (base + g) + d] + out[d] : out[d];
   }

@@ -162,6 +162,44 @@ def test_resistance_matches_oracle(cluster):
     print(f"polydisperse resistance, 6 spheres p = 6: GMRES {info['iters']} (M0), mixed {info2['iters']}")
 
 
+def test_bordered_mobility_operator_and_m0(cluster):
+    from paper_1707_06551_amd import bie
+    c, a, s, g = cluster
+    ops = Operators(g)
+    x = np.random.default_rng(10).standard_normal(3 * g.N + 6 * g.nb)
+    out = host(s.apply(bie.OP_MOBILITY, dev(x)))
+    ref = ops.apply_mobility(x)
+    assert rel_err(out, ref) < 1e-11, (rel_err(out, ref), max_rel(out, ref))
+    for rad in (0.4, 2.5):
+        s1 = bie.Spheres(np.array([[0.2, 0.1, -0.3]]), 7, radii=[rad])
+        y = np.random.default_rng(11).standard_normal(3 * s1.N + 6)
+        z = host(s1.apply_precond(bie.OP_MOBILITY, s1.apply(bie.OP_MOBILITY, dev(y)), precond=bie.PC_M0))
+        assert max_rel(z, y) < 1e-12, rad
+        s1.close()
+
+
+def test_mobility_matches_oracle(cluster):
+    from oracle import solvers
+    from paper_1707_06551_amd import bie
+    c, a, s, g = cluster
+    rng = np.random.default_rng(12)
+    F = rng.standard_normal((g.nb, 3))
+    T = rng.standard_normal((g.nb, 3))
+    v, om, _mu, info = s.solve_mobility(F, T, tol=1e-12, precond=bie.PC_M0)
+    assert info["converged"], info
+    v_o, om_o, _mu_o, _i = solvers.solve_mobility(g, F, T, method="lu")
+    assert rel_err(v, v_o) < 1e-9 and rel_err(om, om_o) < 1e-9, (rel_err(v, v_o), rel_err(om, om_o))
+    v2, om2, _m2, info2 = s.solve_mobility(F, T, tol=1e-10, precision=bie.MIXED, precond=bie.PC_M0)
+    assert info2["converged"] and rel_err(v2, v_o) < 1e-8 and rel_err(om2, om_o) < 1e-8
+    print(f"polydisperse mobility, 6 spheres p = 6: GMRES {info['iters']} (M0), mixed {info2['iters']}")
+    # an isolated sphere of radius a: v = F / (6 pi a), omega = T / (8 pi a^3)
+    s1 = bie.Spheres(np.array([[1.0, 2.0, 3.0]]), 6, radii=[0.7])
+    v1, o1, _m, i1 = s1.solve_mobility(F[:1], T[:1], tol=1e-13, precond=bie.PC_M0)
+    assert np.abs(v1 - F[:1] / (6 * math.pi * 0.7)).max() < 1e-12
+    assert np.abs(o1 - T[:1] / (8 * math.pi * 0.7 ** 3)).max() < 1e-12
+    s1.close()
+
+
 def test_porous_media_solve_matches_oracle(cluster):
     # Problem 1: spheres held fixed in a uniform stream U, (1/2 + S + D) mu = -U
     from paper_1707_06551_amd import bie
@@ -196,9 +234,9 @@ def test_polydisperse_rejects_unit_only_features(cluster):
     c, a, s, g = cluster
     mu = dev(np.zeros(3 * g.N))
     with pytest.raises(bie.BieError):
-        s.apply(bie.OP_MOBILITY, dev(np.zeros(3 * g.N + 6 * g.nb)))
+        s.apply(bie.OP_KL_BIE, mu)
     with pytest.raises(bie.BieError):
-        s.solve_mobility(np.zeros((g.nb, 3)), np.ones((g.nb, 3)))
+        s.solve_mobility_traction(np.zeros((g.nb, 3)), np.ones((g.nb, 3)))
     with pytest.raises(bie.BieError):
         s.solve_resistance(np.zeros((g.nb, 3)), np.ones((g.nb, 3)), precond=bie.PC_M0 | bie.PC_RIGID)
     with pytest.raises(bie.BieError):

@@ -152,3 +152,31 @@ def test_resistance_scales_with_the_configuration():
     F2, T2, _p, _i = solvers.solve_resistance(gs, v, zero, tol=1e-12)
     assert np.abs(F2 - lam * F1).max() < 1e-3 * np.abs(F1).max()
     assert np.abs(T2 - lam ** 2 * T1).max() < 1e-3 * np.abs(T1).max()
+
+
+def test_isolated_sphere_of_radius_a_mobility():
+    # bordered mobility form on one sphere of radius a: v = F / (6 pi a), omega = T / (8 pi a^3)
+    from oracle import solvers
+    a = 1.7
+    g = Geometry(np.array([[0.0, 1.0, 2.0]]), 6, radii=[a])
+    F = np.array([[0.5, -1.5, 0.25]])
+    T = np.array([[-0.4, 0.9, 1.3]])
+    v, om, _mu, info = solvers.solve_mobility(g, F, T, method="lu")
+    assert np.abs(v - F / (6 * math.pi * a)).max() < 1e-12
+    assert np.abs(om - T / (8 * math.pi * a ** 3)).max() < 1e-12
+
+
+def test_mobility_inverts_resistance_with_radii():
+    # two spheres of different radii: the mobility solve driven by the resistance solve's
+    # forces and torques returns the imposed rigid motions (both forms are discretised
+    # from the same layer operators, so they agree to the discretisation error)
+    from oracle import solvers
+    c = np.array([[0.0, 0.0, 0.0], [2.0, 0.4, -0.3]])
+    a = np.array([1.0, 0.6])
+    g = Geometry(c, 8, radii=a)
+    rng = np.random.default_rng(9)
+    v = rng.standard_normal((2, 3))
+    om = rng.standard_normal((2, 3))
+    F, T, _psi, _i = solvers.solve_resistance(g, v, om, tol=1e-12)
+    v2, om2, _mu, _i2 = solvers.solve_mobility(g, F, T, tol=1e-12)
+    assert np.abs(v2 - v).max() < 1e-5 and np.abs(om2 - om).max() < 1e-5
