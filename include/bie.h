@@ -106,14 +106,14 @@ int bie_build_spheres(const double* centres, int64_t n_spheres, const bie_opts* 
  * Near pairs: |c_t - c_s| - a_t - a_s < near_gap * a_s (Eq. 4.5 with the gap measured in
  * the source's radius; directed).  Overlap: |c_t - c_s| < a_t + a_s -> BIE_EOVERLAP.  When
  * some radius differs from 1 the context supports bie_apply_bio with BIE_OP_S, _D,
- * _SD_BIE, _DN_BIE, _MOBILITY and _K, bie_solve with those second-kind forms (porous
- * media, Problem 1, with BIE_OP_SD_BIE), bie_solve_resistance (Problem 5: the moments
- * carry a^2 and a^3; an isolated sphere gives F = 6 pi a v, T = 8 pi a^3 omega) and
- * bie_solve_mobility (v = F/(6 pi a), omega = T/(8 pi a^3) for an isolated sphere), with
- * BIE_PC_NONE or BIE_PC_M0 (per-sphere isolated inverses), the transforms, nodes and near
- * pairs; every other entry point (BIE_OP_KL_BIE and the traction-form mobility solve, the
- * learned and rigid-mode corrections, Laplace, fluid points) returns BIE_EINVAL, as does
- * near_method 1. */
+ * _SD_BIE, _DN_BIE, _MOBILITY, _K and _KL_BIE, bie_solve with the second-kind forms
+ * (porous media, Problem 1, with BIE_OP_SD_BIE), bie_solve_resistance (Problem 5: the
+ * moments carry a^2 and a^3; an isolated sphere gives F = 6 pi a v, T = 8 pi a^3 omega),
+ * bie_solve_mobility and bie_solve_mobility_traction (rho_k = F_k/(4 pi a^2) +
+ * 3/(8 pi a^4) T_k x (x - c_k); v = F/(6 pi a), omega = T/(8 pi a^3) for an isolated
+ * sphere), with BIE_PC_NONE or BIE_PC_M0 (per-sphere isolated inverses), the transforms,
+ * nodes and near pairs; the learned and rigid-mode corrections, the Laplace / magnetic
+ * problem and fluid points return BIE_EINVAL, as does near_method 1. */
 int bie_build_spheres_radii(const double* centres, const double* radii, int64_t n_spheres, const bie_opts* opts,
                             bie_ctx** out);
 

@@ -284,7 +284,7 @@ class TractionOps:
         F, T = self.ops.moments(mu)
         F, T = F[..., 0], T[..., 0]
         k = g.sphere_of
-        return F[k] + np.cross(T[k], g.xhat)
+        return F[k] + np.cross(T[k], g.nodes - g.centres[k])
 
     def apply_KL_BIE(self, mu):
         """(1/2 I + sum_k (K_k + L_k))[mu], the left side of Eq. 5.8."""
@@ -293,18 +293,22 @@ class TractionOps:
 
 
 def force_density(geom, F, T):
-    """rho of Eq. 5.7 on every node: F_k/(4 pi) + 3/(8 pi) T_k x (x - c_k)."""
+    """rho of Eq. 5.7 on every node: F_k/(4 pi a^2) + 3/(8 pi a^4) T_k x (x - c_k) on a
+    sphere of radius a (area 4 pi a^2, int (x-c) x (T x (x-c)) = 8 pi a^4 / 3 T)."""
     k = geom.sphere_of
-    return np.asarray(F, float)[k] / (4.0 * math.pi) + 3.0 / (8.0 * math.pi) * np.cross(np.asarray(T, float)[k],
-                                                                                         geom.xhat)
+    a = geom.radii[k][:, None]
+    return (np.asarray(F, float)[k] / (4.0 * math.pi * a ** 2)
+            + 3.0 / (8.0 * math.pi * a ** 4) * np.cross(np.asarray(T, float)[k], geom.nodes - geom.centres[k]))
 
 
 def rigid_motion(geom, u):
-    """(v_k, omega_k) from the velocity u on the nodes: (1/4 pi) int u, 3/(8 pi) int (x - c) x u."""
+    """(v_k, omega_k) from the velocity u on the nodes: (1/(4 pi a^2)) int u and
+    3/(8 pi a^4) int (x - c) x u (the rigid motion of u on a sphere of radius a)."""
     wu = u * geom.w[:, None]
-    v = wu.reshape(geom.nb, geom.P, 3).sum(axis=1) / (4.0 * math.pi)
-    om = np.cross(geom.xhat, wu).reshape(geom.nb, geom.P, 3).sum(axis=1) * 3.0 / (8.0 * math.pi)
-    return v, om
+    a = geom.radii[:, None]
+    v = wu.reshape(geom.nb, geom.P, 3).sum(axis=1) / (4.0 * math.pi * a ** 2)
+    om = np.cross(geom.nodes - geom.centres[geom.sphere_of], wu).reshape(geom.nb, geom.P, 3).sum(axis=1)
+    return v, om * 3.0 / (8.0 * math.pi * a ** 4)
 
 
 def solve_mobility_traction(geom, F, T, tol=1e-11, restart=100, max_iter=1000):

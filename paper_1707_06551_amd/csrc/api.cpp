@@ -49,8 +49,6 @@ void apply(bie_ctx* c, int op, int precision, const double* mu, double* u) {
   const OpSpec spec = op_spec(base);
   if (spec.traction && c->near_method != 0)
     throw Error{BIE_EINVAL, "the traction operator supports near_method 0 (series at the target nodes) only"};
-  if (c->poly && spec.rigid_local)
-    throw Error{BIE_EINVAL, "spheres of several radii: BIE_OP_KL_BIE is built for unit spheres only"};
   VshCall v;
   v.mu = mu;
   v.u = u;
@@ -74,7 +72,8 @@ void apply(bie_ctx* c, int op, int precision, const double* mu, double* u) {
   }
   launch_vsh(c, precision, v);
   // L of Eq. 5.8 on the own sphere: int mu + (int (y - c) x mu) x (x - c)
-  if (spec.rigid_local && (stages & BIE_STAGE_SELF)) add_rigid_local(c, c->moments.as<double>(), u);
+  if (spec.rigid_local && (stages & BIE_STAGE_SELF))
+    add_rigid_local(c, c->moments.as<double>(), u, c->poly ? c->radius_d.as<double>() : nullptr);
   if (stages & BIE_STAGE_NEAR) {
     if (spec.traction)
       launch_near_traction(c, u);
@@ -102,6 +101,33 @@ void dev_precond_m0(bie_ctx* c, int op_base, int precision, const double* r, dou
   v.u = z;
   v.do_self = true;
   v.c_identity = 2.0;
+  if (c->poly && op_base == BIE_OP_KL_BIE) {
+    // 1/2 + K_pv + L on a sphere of radius a: D_+'s eigenvalues except W_1 -> 4 pi a^2 and
+    // X_1 -> 8 pi a^4 / 3 (L with moments a^2, a^3 and lever arm a)
+    for (int n = 0; n <= c->p; ++n) {
+      double ed[3];
+      eig_Dplus(n, ed);
+      for (int f = 0; f < 3; ++f) {
+        const bool exists = (f == 0) || n >= 1;
+        v.lamS[f][n] = 0.0;
+        if (!exists) {
+          v.lam[f][n] = 0.0;
+        } else if (n == 1 && f > 0) {
+          v.lamS[f][n] = (f == 1) ? 1.0 / (4.0 * M_PI) : 3.0 / (8.0 * M_PI);
+          v.lam[f][n] = -2.0;
+        } else {
+          v.lam[f][n] = 1.0 / ed[f] - 2.0;
+        }
+      }
+    }
+    v.lam_pow[0] = -1;
+    v.lam_pow[1] = -2;
+    v.lam_pow[2] = -4;
+    v.radius = c->radius_d.as<double>();
+    v.lam_mode = 3;
+    launch_vsh(c, precision, v);
+    return;
+  }
   if (c->poly && op_base == BIE_OP_DN_BIE) {
     // completed form on a sphere of radius a: the completion's moments carry a^2 and a^3
     // at distance a, so W_1 -> 3/(2a) and X_1 -> 3/a; V_1 (5/3, coupling 5/12) and the
@@ -197,9 +223,8 @@ void apply_precond(bie_ctx* c, int op_base, int precision, int precond, const do
   const int64_t n = 3 * c->N + (op_base == BIE_OP_MOBILITY ? 6 * c->nb : 0);
   const bool rigid = (precond & BIE_PC_RIGID) != 0;
   const int base = precond & ~BIE_PC_RIGID;
-  if (c->poly && (op_base == BIE_OP_KL_BIE || (precond & ~BIE_PC_M0) != 0))
-    throw Error{BIE_EINVAL, "spheres of several radii: preconditioners BIE_PC_NONE / BIE_PC_M0 of "
-                            "BIE_OP_SD_BIE, BIE_OP_DN_BIE and BIE_OP_MOBILITY only"};
+  if (c->poly && (precond & ~BIE_PC_M0) != 0)
+    throw Error{BIE_EINVAL, "spheres of several radii: preconditioners BIE_PC_NONE and BIE_PC_M0 only"};
   if (rigid && base == BIE_PC_NONE) throw Error{BIE_EINVAL, "BIE_PC_RIGID needs BIE_PC_M0 or BIE_PC_MLP"};
   if (rigid && c->nb > RIGID_MAX_SPHERES) throw Error{BIE_EINVAL, "BIE_PC_RIGID: too many spheres for the coarse solve"};
   switch (base) {
@@ -466,23 +491,25 @@ int bie_solve_mobility_traction(bie_ctx* c, const double* F, const double* T, co
   }
   int rc = BIE_OK;
   BIE_TRY({
-    bie::require_unit(c, "bie_solve_mobility_traction");
     const int64_t n3 = 3 * c->N, nb = c->nb;
     bie::DevBuf rho, rhs, x, ab;
     rho.alloc(n3 * sizeof(double));
     rhs.alloc(n3 * sizeof(double));
     x.alloc(n3 * sizeof(double));
     ab.alloc(6 * nb * sizeof(double));
-    // rho of Eq. 5.7: F_k / (4 pi) + 3/(8 pi) T_k x (x - c_k)
+    // rho of Eq. 5.7: F_k / (4 pi a^2) + 3/(8 pi a^4) T_k x (x - c_k) on a sphere of
+    // radius a (int rho = F_k, int (x - c_k) x rho = T_k); x - c_k = a o
     std::vector<double> h(6 * nb);
-    for (int64_t k = 0; k < nb; ++k)
+    for (int64_t k = 0; k < nb; ++k) {
+      const double a = c->radius[k];
       for (int d = 0; d < 3; ++d) {
-        h[6 * k + d] = F[3 * k + d] / (4.0 * M_PI);
-        h[6 * k + 3 + d] = 3.0 * T[3 * k + d] / (8.0 * M_PI);
+        h[6 * k + d] = F[3 * k + d] / (4.0 * M_PI * a * a);
+        h[6 * k + 3 + d] = 3.0 * T[3 * k + d] / (8.0 * M_PI * a * a * a * a);
       }
+    }
     BIE_HIP(hipMemcpyAsync(ab.ptr, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
     bie::dev_fill(c, rho.as<double>(), 0.0, n3);
-    bie::add_rigid_local(c, ab.as<double>(), rho.as<double>());
+    bie::add_rigid_local(c, ab.as<double>(), rho.as<double>(), c->poly ? c->radius_d.as<double>() : nullptr);
     // right-hand side of Eq. 5.8: -(1/2 rho + sum_k K_k[rho]), float64
     bie::apply(c, BIE_OP_K, BIE_FP64, rho.as<double>(), rhs.as<double>());
     bie::dev_axpby(c, -0.5, rho.as<double>(), -1.0, rhs.as<double>(), n3);
@@ -494,10 +521,12 @@ int bie_solve_mobility_traction(bie_ctx* c, const double* F, const double* T, co
     bie::rigid_restrict(c, rhs.as<double>(), ab.as<double>());
     BIE_HIP(hipMemcpyAsync(h.data(), ab.ptr, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     BIE_HIP(hipStreamSynchronize(c->stream));
+    // the restriction works on unit offsets and weights: (1/4pi) sum w u is already the
+    // mean velocity, (3/8pi) sum w o x u carries a^3 / a^4 too few powers of a: divide by a
     for (int64_t k = 0; k < nb; ++k)
       for (int d = 0; d < 3; ++d) {
         v[3 * k + d] = h[6 * k + d];
-        omega[3 * k + d] = h[6 * k + 3 + d];
+        omega[3 * k + d] = h[6 * k + 3 + d] / c->radius[k];
       }
     rho.release();
     rhs.release();

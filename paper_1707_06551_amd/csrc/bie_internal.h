@@ -145,10 +145,11 @@ struct VshCall {
   double lam[3][33] = {};
   // per-sphere multipliers for spheres of radius a_k (radius != nullptr):
   //   lam_mode 1: a_k lamS + lam (operator);  2: 1 / (a_k lamS + lam) - 2 (M0), 0 where
-  //   both vanish;  3: lamS / a_k + lam (M0 of the completed form).  With radius set the
-  //   moments carry a_k^2 (force) and a_k^3 (torque)
+  //   both vanish;  3: lamS a_k^lam_pow[f] + lam (M0 of the completed and traction forms).
+  //   With radius set the moments carry a_k^2 (force) and a_k^3 (torque)
   const double* radius = nullptr;
   int lam_mode = 0;
+  int lam_pow[3] = {-1, -1, -1};
   double lamS[3][33] = {};
 };
 void launch_vsh(bie_ctx* c, int precision, const VshCall& v);
@@ -185,7 +186,8 @@ void rigid_restrict(bie_ctx* c, const double* f, double* xi);
 
 // single-layer traction K on the near pairs; u += a_k + b_k x (x - c_k) (ab = nb x 6)
 void launch_near_traction(bie_ctx* c, double* u);
-void add_rigid_local(bie_ctx* c, const double* ab, double* u);
+// with radius (nullable): u += a_k + r_k b_k x o, i.e. b_k x (x - c_k) on a sphere of radius r_k
+void add_rigid_local(bie_ctx* c, const double* ab, double* u, const double* radius = nullptr);
 
 // Laplace / magnetostatic operators (laplace.hip); OP_LAPLACE is the solver's internal
 // operator code for (1/2 I + eta K^L) on N scalar unknowns

@@ -302,12 +302,15 @@ __global__ __launch_bounds__(256) void near_traction_kernel(TracParams a) {
   }
 }
 
-// u += a_k + b_k x o at every node of sphere k, ab = nb x 6 (a, b).
-__global__ void k_add_rigid(const double* ab, const double* otab, int P, int64_t N, double* u) {
+// u += a_k + b_k x (x - c_k) at every node of sphere k, ab = nb x 6 (a, b); x - c_k = r_k o
+// (r_k = 1 without radii).
+__global__ void k_add_rigid(const double* ab, const double* otab, const double* radius, int P, int64_t N,
+                            double* u) {
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < N; g += (int64_t)gridDim.x * blockDim.x) {
     const int64_t k = g / P;
     const int li = (int)(g - k * P);
-    const double* o = otab + 4 * li;
+    const double r = radius ? radius[k] : 1.0;
+    const double o[3] = {r * otab[4 * li], r * otab[4 * li + 1], r * otab[4 * li + 2]};
     const double* v = ab + 6 * k;
     u[3 * g + 0] += v[0] + (v[4] * o[2] - v[5] * o[1]);
     u[3 * g + 1] += v[1] + (v[5] * o[0] - v[3] * o[2]);
@@ -349,9 +352,9 @@ void launch_near_traction(bie_ctx* c, double* u) {
   BIE_HIP(hipGetLastError());
 }
 
-void add_rigid_local(bie_ctx* c, const double* ab, double* u) {
+void add_rigid_local(bie_ctx* c, const double* ab, double* u, const double* radius) {
   const int blocks = (int)std::min<int64_t>((c->N + 255) / 256, 4096);
-  k_add_rigid<<<dim3(blocks), dim3(256), 0, c->stream>>>(ab, c->otab.as<double>(), c->P, c->N, u);
+  k_add_rigid<<<dim3(blocks), dim3(256), 0, c->stream>>>(ab, c->otab.as<double>(), radius, c->P, c->N, u);
   BIE_HIP(hipGetLastError());
 }
 

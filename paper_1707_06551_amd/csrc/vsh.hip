@@ -34,8 +34,9 @@ struct VshParams {
   int accumulate;  // u += synthesis (else u = synthesis)
   double wv1;      // n = 1 coupling: V'_1 += wv1 * W_1 (preconditioner of the completed form)
   double lam[3][33];
-  const double* radius;  // per-sphere radii for lam_mode 1, 2 (see VshCall)
+  const double* radius;  // per-sphere radii for lam_mode 1, 2, 3 (see VshCall)
   int lam_mode;
+  int lam_pow[3];
   double lamS[3][33];
 };
 
@@ -183,7 +184,9 @@ __global__ __launch_bounds__(256) void vsh_kernel(VshParams a) {
           double l3[3];
           for (int f = 0; f < 3; ++f) {
             if (a.lam_mode == 3) {
-              l3[f] = a.lamS[f][n] / rad + a.lam[f][n];
+              double sc = 1.0;
+              for (int e = 0; e < -a.lam_pow[f]; ++e) sc /= rad;
+              l3[f] = a.lamS[f][n] * sc + a.lam[f][n];
             } else {
               const double s = rad * a.lamS[f][n] + a.lam[f][n];
               l3[f] = (a.lam_mode == 1) ? s : (s != 0.0 ? 1.0 / s - 2.0 : 0.0);
@@ -398,6 +401,7 @@ void launch_vsh(bie_ctx* c, int precision, const VshCall& v) {
     for (int n = 0; n < 33; ++n) a.lam[f][n] = v.lam[f][n];
   a.radius = v.radius;
   a.lam_mode = v.radius ? v.lam_mode : 0;
+  for (int f = 0; f < 3; ++f) a.lam_pow[f] = v.lam_pow[f];
   for (int f = 0; f < 3; ++f)
     for (int n = 0; n < 33; ++n) a.lamS[f][n] = v.lamS[f][n];
   const size_t sm = vsh_smem(c, f32 ? sizeof(float) : sizeof(double));

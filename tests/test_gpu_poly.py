@@ -200,6 +200,37 @@ def test_mobility_matches_oracle(cluster):
     s1.close()
 
 
+def test_traction_form_with_radii(cluster):
+    # 1/2 I + K + L and Problem 2 in the paper's form (Eqs. 5.7-5.8) on spheres of radii
+    from paper_1707_06551_amd import bie
+    c, a, s, g = cluster
+    to = tr.TractionOps(g)
+    mu = np.random.default_rng(13).standard_normal((g.N, 3))
+    out = host(s.apply(bie.OP_KL_BIE, dev(mu))).reshape(g.N, 3)
+    ref = to.apply_KL_BIE(mu)
+    assert rel_err(out, ref) < 1e-11, (rel_err(out, ref), max_rel(out, ref))
+    for rad in (0.4, 2.5):
+        s1 = bie.Spheres(np.array([[0.2, 0.1, -0.3]]), 7, radii=[rad])
+        y = np.random.default_rng(14).standard_normal(3 * s1.N)
+        z = host(s1.apply_precond(bie.OP_KL_BIE, s1.apply(bie.OP_KL_BIE, dev(y)), precond=bie.PC_M0))
+        assert max_rel(z, y) < 1e-12, rad
+        F1 = np.array([[0.7, -0.2, 1.1]])
+        T1 = np.array([[0.1, 0.9, -0.6]])
+        v1, o1, _m, i1 = s1.solve_mobility_traction(F1, T1, tol=1e-13)
+        assert np.abs(v1 - F1 / (6 * math.pi * rad)).max() < 1e-12
+        assert np.abs(o1 - T1 / (8 * math.pi * rad ** 3)).max() < 1e-12
+        s1.close()
+    rng = np.random.default_rng(15)
+    F = rng.standard_normal((g.nb, 3))
+    T = rng.standard_normal((g.nb, 3))
+    v, om, mu_d, info = s.solve_mobility_traction(F, T, tol=1e-12, want_mu=True)
+    assert info["converged"], info
+    v_o, om_o, mu_o, _i = tr.solve_mobility_traction(g, F, T, tol=1e-12)
+    assert rel_err(v, v_o) < 1e-9 and rel_err(om, om_o) < 1e-9, (rel_err(v, v_o), rel_err(om, om_o))
+    assert rel_err(host(mu_d).reshape(g.N, 3), mu_o) < 1e-8
+    print(f"polydisperse traction-form mobility, 6 spheres p = 6: GMRES {info['iters']}")
+
+
 def test_porous_media_solve_matches_oracle(cluster):
     # Problem 1: spheres held fixed in a uniform stream U, (1/2 + S + D) mu = -U
     from paper_1707_06551_amd import bie
@@ -234,9 +265,9 @@ def test_polydisperse_rejects_unit_only_features(cluster):
     c, a, s, g = cluster
     mu = dev(np.zeros(3 * g.N))
     with pytest.raises(bie.BieError):
-        s.apply(bie.OP_KL_BIE, mu)
+        s.eval_field(bie.OP_SD_BIE, mu, np.array([[10.0, 10.0, 10.0]]))
     with pytest.raises(bie.BieError):
-        s.solve_mobility_traction(np.zeros((g.nb, 3)), np.ones((g.nb, 3)))
+        s.solve_magnetic([0.0, 0.0, 1.0], 0.5)
     with pytest.raises(bie.BieError):
         s.solve_resistance(np.zeros((g.nb, 3)), np.ones((g.nb, 3)), precond=bie.PC_M0 | bie.PC_RIGID)
     with pytest.raises(bie.BieError):

@@ -180,3 +180,25 @@ def test_mobility_inverts_resistance_with_radii():
     F, T, _psi, _i = solvers.solve_resistance(g, v, om, tol=1e-12)
     v2, om2, _mu, _i2 = solvers.solve_mobility(g, F, T, tol=1e-12)
     assert np.abs(v2 - v).max() < 1e-5 and np.abs(om2 - om).max() < 1e-5
+
+
+def test_traction_mobility_with_radii():
+    # Problem 2 in the paper's form on spheres of radius a: the isolated sphere moves
+    # with F/(6 pi a), T/(8 pi a^3); two spheres of different radii agree with the
+    # bordered form to the discretisation error (p = 8, gap 0.46 = 0.77 of the small
+    # radius: ~2e-4)
+    from oracle import solvers
+    g1 = Geometry(np.array([[0.3, 0.0, -0.4]]), 6, radii=[0.55])
+    F = np.array([[0.7, -0.2, 1.1]])
+    T = np.array([[0.1, 0.9, -0.6]])
+    v, om, mu, _i = tr.solve_mobility_traction(g1, F, T)
+    assert np.abs(v - F / (6 * math.pi * 0.55)).max() < 1e-12
+    assert np.abs(om - T / (8 * math.pi * 0.55 ** 3)).max() < 1e-12
+    c = np.array([[0.0, 0.0, 0.0], [2.0, 0.4, -0.3]])
+    g = Geometry(c, 8, radii=[1.0, 0.6])
+    rng = np.random.default_rng(10)
+    F = rng.standard_normal((2, 3))
+    T = rng.standard_normal((2, 3))
+    v1, o1, _m1, _i1 = tr.solve_mobility_traction(g, F, T, tol=1e-12)
+    v2, o2, _m2, _i2 = solvers.solve_mobility(g, F, T, tol=1e-12)
+    assert np.abs(v1 - v2).max() < 1e-3 * np.abs(v2).max() and np.abs(o1 - o2).max() < 1e-3 * np.abs(o2).max()
