@@ -111,9 +111,10 @@ int bie_build_spheres(const double* centres, int64_t n_spheres, const bie_opts* 
  * moments carry a^2 and a^3; an isolated sphere gives F = 6 pi a v, T = 8 pi a^3 omega),
  * bie_solve_mobility and bie_solve_mobility_traction (rho_k = F_k/(4 pi a^2) +
  * 3/(8 pi a^4) T_k x (x - c_k); v = F/(6 pi a), omega = T/(8 pi a^3) for an isolated
- * sphere), with BIE_PC_NONE or BIE_PC_M0 (per-sphere isolated inverses), the transforms,
- * nodes and near pairs; the learned and rigid-mode corrections, the Laplace / magnetic
- * problem and fluid points return BIE_EINVAL, as does near_method 1. */
+ * sphere), with BIE_PC_NONE or BIE_PC_M0 (per-sphere isolated inverses), bie_eval_field
+ * (near test |x - c_k| - a_k < near_gap a_k), the transforms, nodes and near pairs; the
+ * learned and rigid-mode corrections and the Laplace / magnetic problem return
+ * BIE_EINVAL, as does near_method 1. */
 int bie_build_spheres_radii(const double* centres, const double* radii, int64_t n_spheres, const bie_opts* opts,
                             bie_ctx** out);
 
@@ -238,9 +239,9 @@ int bie_apply_precond(bie_ctx* ctx, int op, int precision, int precond, const do
  * BIE_OP_DN_BIE = D plus the completion flow of Eqs. 5.18-5.19; the identity term of
  * the second-kind forms is a surface term and is not added) of the node density mu
  * (device float64, 3N) at n_targets points (device float64, n_targets x 3, row-major)
- * -> u (device float64, n_targets x 3).  Per sphere k: |x - c_k| - 1 < near_gap takes the
- * exterior series of Eqs. 3.6-3.11 (Section 3), otherwise the smooth quadrature of Eq.
- * 4.4.  Float64.  A point inside or on a sphere gets NaN and the call returns BIE_EINVAL
+ * -> u (device float64, n_targets x 3).  Per sphere k: |x - c_k| - a_k < near_gap a_k
+ * (a_k = 1 for unit spheres) takes the exterior series of Eqs. 3.6-3.11 (Section 3),
+ * otherwise the smooth quadrature of Eq. 4.4.  Float64.  A point inside or on a sphere gets NaN and the call returns BIE_EINVAL
  * after writing the others.  n_targets = 0 is a no-op.  Synchronises the stream. */
 int bie_eval_field(bie_ctx* ctx, int op, const double* mu, int64_t n_targets, const double* targets, double* u);
 

@@ -37,17 +37,18 @@ def evaluate(geom, mu, x, op="SD_BIE", ops=None):
     g = geom
     x = np.asarray(x, dtype=np.float64).reshape(-1, 3)
     mu = np.asarray(mu, dtype=np.float64).reshape(g.N, 3)
-    dist = np.linalg.norm(x[:, None, :] - g.centres[None, :, :], axis=-1) - 1.0   # (K, nb)
+    # distance to the surface; spheres of radius a: near when below d* a (Eq. 4.5 scaled)
+    dist = np.linalg.norm(x[:, None, :] - g.centres[None, :, :], axis=-1) - g.radii[None, :]
     if (dist <= 0.0).any():
         raise ValueError("evaluation point inside or on a sphere")
     q = mu * g.w[:, None]
     out = np.zeros((x.shape[0], 3))
     for k in range(g.nb):
         sl = g.sphere_nodes(k)
-        near = dist[:, k] < g.near_gap
+        near = dist[:, k] < g.near_gap * g.radii[k]
         if near.any():
             coef = ops.coefficients(mu[:, :, None], k)
-            out[near] += ops.near_field_from(coef, g.centres[k], x[near], a_s, a_d)[..., 0]
+            out[near] += ops.near_field_from(coef, g.centres[k], x[near], a_s, a_d, g.radii[k])[..., 0]
         far = ~near
         if far.any():
             out[far] += kernels.direct_sum(x[far], g.nodes[sl], g.xhat[sl], q[sl][:, :, None], a_s, a_d)[..., 0]

@@ -605,7 +605,7 @@ int bie_eval_field(bie_ctx* c, int op, const double* mu, int64_t n_targets, cons
     bie::set_error("null context");
     return BIE_EINVAL;
   }
-  BIE_TRY(bie::require_unit(c, "bie_eval_field"); bie::eval_field(c, op, mu, n_targets, targets, u));
+  BIE_TRY(bie::eval_field(c, op, mu, n_targets, targets, u));
   return BIE_OK;
 }
 

@@ -9,7 +9,10 @@
 // over its nodes.  Float64 throughout.  One thread per target; a work-group stages the
 // strengths w mu of one source sphere at a time in LDS (broadcast reads) and the
 // Legendre recurrence table once.  A point inside or on a sphere gets NaN and raises
-// a flag the host turns into BIE_EINVAL.
+// a flag the host turns into BIE_EINVAL.  Spheres of radius a_k: the test reads
+// |x - c_k| - a_k < d* a_k, the series is evaluated at (x - c_k)/a_k with its single-layer
+// part scaled by a_k (constants staged per sphere), the quadrature uses the nodes
+// c_k + a_k o and weights a_k^2 w.
 #include "bie_internal.h"
 #include "series.h"
 
@@ -27,17 +30,26 @@ struct FieldParams {
   const double* rec;       // ncoef x 6
   double* u;               // M x 3
   int* bad;                // set when a target lies inside or on a sphere
+  const double* radius;    // nb radii, or null (unit spheres)
   int64_t M, nb;
   int P, p, mmax, ncoef, completion;
   double near_gap, a_s, a_d;
-  double kvv[33], kww[33], kwv[33], kxx[33];
+  double kvv[33], kww[33], kwv[33], kxx[33];  // series constants (double-layer part with radii)
+  double sv[33], sw[33], swv[33], sx[33];     // single-layer part, scaled by a_k (radii only)
+};
+
+struct FieldK {
+  int p, mmax, ncoef;
+  const double *kvv, *kww, *kwv, *kxx;
 };
 
 __global__ __launch_bounds__(256) void field_kernel(FieldParams a) {
   extern __shared__ __align__(16) double sm[];
   double* qs = sm;                    // P x 4 strengths of the current sphere
   double* rec = sm + 4 * a.P;         // ncoef x 6
+  double* kc = rec + 6 * a.ncoef;     // 4 x 33 series constants of the current sphere
   for (int i = threadIdx.x; i < 6 * a.ncoef; i += blockDim.x) rec[i] = a.rec[i];
+  const FieldK kk{a.p, a.mmax, a.ncoef, kc, kc + 33, kc + 66, kc + 99};
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = t < a.M;
   double xx = 0, xy = 0, xz = 0;
@@ -50,25 +62,36 @@ __global__ __launch_bounds__(256) void field_kernel(FieldParams a) {
   double ux = 0, uy = 0, uz = 0;
   bool inside = false;
   for (int64_t k = 0; k < a.nb; ++k) {
+    const double ak = a.radius ? a.radius[k] : 1.0;
     __syncthreads();
     for (int i = threadIdx.x; i < 4 * a.P; i += blockDim.x) qs[i] = a.q[4 * k * a.P + i];
+    for (int n = threadIdx.x; n <= a.p; n += blockDim.x) {
+      const bool r = a.radius != nullptr;
+      kc[n] = r ? fma(ak, a.sv[n], a.kvv[n]) : a.kvv[n];
+      kc[33 + n] = r ? fma(ak, a.sw[n], a.kww[n]) : a.kww[n];
+      kc[66 + n] = r ? fma(ak, a.swv[n], a.kwv[n]) : a.kwv[n];
+      kc[99 + n] = r ? fma(ak, a.sx[n], a.kxx[n]) : a.kxx[n];
+    }
     __syncthreads();
     if (!valid) continue;
     const double dx = xx - a.centres4[4 * k], dy = xy - a.centres4[4 * k + 1], dz = xz - a.centres4[4 * k + 2];
-    const double dist = sqrt(dx * dx + dy * dy + dz * dz) - 1.0;
+    const double dist = sqrt(dx * dx + dy * dy + dz * dz) - ak;
     if (!(dist > 0.0)) {
       inside = true;
       continue;
     }
-    if (dist < a.near_gap) {
-      exterior_series(a, a.coef + (size_t)k * 6 * a.ncoef, rec, dx, dy, dz, ux, uy, uz);
+    if (dist < a.near_gap * ak) {
+      const double iak = 1.0 / ak;
+      exterior_series(kk, a.coef + (size_t)k * 6 * a.ncoef, rec, dx * iak, dy * iak, dz * iak, ux, uy, uz);
       continue;
     }
+    const double w2 = ak * ak;   // weights a^2 w (strengths q = w mu are per unit sphere)
     double sx = 0, sy = 0, sz = 0;
     for (int i = 0; i < a.P; ++i) {
       const double ox = a.otab[4 * i], oy = a.otab[4 * i + 1], oz = a.otab[4 * i + 2];
-      const double* qi = qs + 4 * i;
-      const double rx = dx - ox, ry = dy - oy, rz = dz - oz;
+      const double* qi0 = qs + 4 * i;
+      const double qi[3] = {w2 * qi0[0], w2 * qi0[1], w2 * qi0[2]};
+      const double rx = dx - ak * ox, ry = dy - ak * oy, rz = dz - ak * oz;
       const double r2 = rx * rx + ry * ry + rz * rz;
       const double ir = 1.0 / sqrt(r2);
       const double ir2 = ir * ir;
@@ -123,6 +146,10 @@ void eval_field(bie_ctx* c, int op_base, const double* mu, int64_t M, const doub
   v.write_q = true;
   v.write_coef = true;
   v.want_moments = spec.completion;
+  if (c->poly) {
+    v.radius = c->radius_d.as<double>();   // moments with a^2, a^3
+    v.lam_mode = 1;
+  }
   launch_vsh(c, BIE_FP64, v);
   int* bad = reinterpret_cast<int*>(c->scal.as<double>());
   BIE_HIP(hipMemsetAsync(bad, 0, sizeof(int), c->stream));
@@ -146,8 +173,14 @@ void eval_field(bie_ctx* c, int op_base, const double* mu, int64_t M, const doub
   a.near_gap = c->near_gap;
   a.a_s = spec.a_s;
   a.a_d = spec.a_d;
-  series_radial(spec.a_s, spec.a_d, c->p, a.kvv, a.kww, a.kwv, a.kxx);
-  const size_t sm = (4 * (size_t)c->P + 6 * (size_t)c->ncoef) * sizeof(double);
+  a.radius = c->poly ? c->radius_d.as<double>() : nullptr;
+  if (c->poly) {
+    series_radial(0.0, spec.a_d, c->p, a.kvv, a.kww, a.kwv, a.kxx);
+    series_radial(spec.a_s, 0.0, c->p, a.sv, a.sw, a.swv, a.sx);
+  } else {
+    series_radial(spec.a_s, spec.a_d, c->p, a.kvv, a.kww, a.kwv, a.kxx);
+  }
+  const size_t sm = (4 * (size_t)c->P + 6 * (size_t)c->ncoef + 4 * 33) * sizeof(double);
   field_kernel<<<dim3((unsigned)((M + 255) / 256)), dim3(256), sm, c->stream>>>(a);
   BIE_HIP(hipGetLastError());
   int hbad = 0;

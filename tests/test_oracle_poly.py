@@ -202,3 +202,28 @@ def test_traction_mobility_with_radii():
     v1, o1, _m1, _i1 = tr.solve_mobility_traction(g, F, T, tol=1e-12)
     v2, o2, _m2, _i2 = solvers.solve_mobility(g, F, T, tol=1e-12)
     assert np.abs(v1 - v2).max() < 1e-3 * np.abs(v2).max() and np.abs(o1 - o2).max() < 1e-3 * np.abs(o2).max()
+
+
+def test_fluid_points_around_a_fixed_sphere_of_radius_a():
+    # Problem 1 on one sphere of radius a, the flow evaluated at fluid points: exterior
+    # series within d* a of the surface (exact for this degree-one density), quadrature
+    # beyond (p = 12: its error at 1.2 a from the surface, 1e-8 - 1.3e-7 by direction)
+    from oracle import field
+    a = 0.45
+    cen = np.array([0.3, -0.2, 0.5])
+    g = Geometry(cen[None, :], 12, near_gap=1.0, radii=[a])
+    ops = Operators(g)
+    U = np.array([0.4, -1.1, 0.7])
+    A = assemble(lambda m: ops.apply("SD_BIE", m.reshape(g.N, 3, -1)).reshape(3 * g.N, -1), 3 * g.N)
+    mu = np.linalg.solve(A, -np.tile(U, g.N)).reshape(g.N, 3)
+    d = np.random.default_rng(11).standard_normal((6, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    x = cen[None, :] + a * np.array([1.02, 1.3, 1.9, 2.2, 3.5, 8.0])[:, None] * d
+    u = U[None, :] + field.evaluate(g, mu, x, "SD_BIE", ops)
+    r = x - cen[None, :]
+    dd = np.linalg.norm(r, axis=1)[:, None]
+    rU = (r @ U)[:, None]
+    ref = U[None, :] - 0.75 * a * (U[None, :] / dd + rU * r / dd ** 3) - 0.25 * a ** 3 * (U[None, :] / dd ** 3
+                                                                                          - 3 * rU * r / dd ** 5)
+    err = np.abs(u - ref).max(axis=1)
+    assert err[:3].max() < 1e-12 and err[3:].max() < 3e-7 and err[4:].max() < 1e-12, err
