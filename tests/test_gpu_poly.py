@@ -85,13 +85,15 @@ def test_stages_match_oracle(cluster, stage):
     assert rel_err(out, ref) < 1e-11, (rel_err(out, ref), max_rel(out, ref))
 
 
-def test_traction_matches_oracle(cluster):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_traction_matches_oracle(cluster, precision):
     from paper_1707_06551_amd import bie
     c, a, s, g = cluster
     mu = np.random.default_rng(3).standard_normal((g.N, 3))
-    out = host(s.apply(bie.OP_K, dev(mu))).reshape(g.N, 3)
+    out = host(s.apply(bie.OP_K, dev(mu), precision=precision)).reshape(g.N, 3)
     ref = tr.TractionOps(g).apply_K(mu)
-    assert rel_err(out, ref) < 1e-11, (rel_err(out, ref), max_rel(out, ref))
+    tol = 1e-11 if precision == 0 else 2e-6
+    assert rel_err(out, ref) < tol, (rel_err(out, ref), max_rel(out, ref))
 
 
 def test_scaled_configuration(cluster):
