@@ -111,10 +111,11 @@ int bie_build_spheres(const double* centres, int64_t n_spheres, const bie_opts* 
  * moments carry a^2 and a^3; an isolated sphere gives F = 6 pi a v, T = 8 pi a^3 omega),
  * bie_solve_mobility and bie_solve_mobility_traction (rho_k = F_k/(4 pi a^2) +
  * 3/(8 pi a^4) T_k x (x - c_k); v = F/(6 pi a), omega = T/(8 pi a^3) for an isolated
- * sphere), with BIE_PC_NONE or BIE_PC_M0 (per-sphere isolated inverses), bie_eval_field
- * (near test |x - c_k| - a_k < near_gap a_k), the transforms, nodes and near pairs; the
- * learned and rigid-mode corrections and the Laplace / magnetic problem return
- * BIE_EINVAL, as does near_method 1. */
+ * sphere), with BIE_PC_NONE or BIE_PC_M0 (per-sphere isolated inverses), the resistance
+ * form also with BIE_PC_M0 | BIE_PC_RIGID (the coarse operator of spheres of radius a,
+ * see BIE_PC_RIGID), bie_eval_field (near test |x - c_k| - a_k < near_gap a_k), the
+ * transforms, nodes and near pairs; the learned correction and the Laplace / magnetic
+ * problem return BIE_EINVAL, as does near_method 1. */
 int bie_build_spheres_radii(const double* centres, const double* radii, int64_t n_spheres, const bie_opts* opts,
                             bie_ctx** out);
 
@@ -163,7 +164,11 @@ int bie_vsh_inverse(bie_ctx* ctx, int precision, const double* coef, double* u);
  * torque the completion flow of Eqs. 5.18-5.19 carries, and M_RPY is the Rotne-Prager-
  * Yamakawa grand mobility of the unit spheres (translation (1/8 pi d)[(1 + 2/(3d^2)) I +
  * (1 - 2/d^2) e e], coupling -[r]_x / (8 pi d^3), rotation -(I - 3 e e)/(16 pi d^3),
- * self blocks I/6pi and I/8pi).  The coarse system is solved on the device by Jacobi-
+ * self blocks I/6pi and I/8pi).  Spheres of radius a (bie_build_spheres_radii): R f =
+ * (int f / (4 pi a^2), 3 int (x - c) x f / (8 pi a^4)), P (a, b) = a + b x (x - c),
+ * S = diag(4 pi a^2, 8 pi a^4 / 3), self blocks I/(6 pi a), I/(8 pi a^3), and the
+ * translation block (1/8 pi d)[(1 + (a_i^2 + a_k^2)/(3d^2)) I + (1 - (a_i^2 + a_k^2)/d^2)
+ * e e].  The coarse system is solved on the device by Jacobi-
  * preconditioned conjugate gradients (float64, relative residual 1e-7, at most 400
  * iterations) with a matrix-free all-pairs product over the centres.  n_b <= 65536
  * (BIE_EINVAL beyond).  Other forms ignore the flag (the mobility form carries its rigid motions as

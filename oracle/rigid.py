@@ -29,6 +29,13 @@ sphere:
   non-overlapping spheres, so it is the one used.
 * For M0, R M0 P = diag(3/2, 3) = (A_c of an isolated sphere)^-1: on one sphere the
   correction vanishes.
+* Spheres of radius a: R f = (int f / (4 pi a^2), 3 int (x - c) x f / (8 pi a^4)) (the
+  mean velocity and rotation of f), P (a, b) = a + b x (x - c), S = diag(4 pi a^2,
+  8 pi a^4 / 3) (the force and torque of a rigid density, Eq. 5.19's N), and M the
+  polydisperse Rotne-Prager-Yamakawa mobility: self blocks I/(6 pi a), I/(8 pi a^3),
+  translation-translation (1/8 pi d)[(1 + (a_i^2 + a_k^2)/(3 d^2)) I +
+  (1 - (a_i^2 + a_k^2)/d^2) e e] (the Stokeslet averaged over both spheres), rotation
+  blocks as above.  R M0 P = diag(3/(2a), 3/a) = (A_c of an isolated sphere)^-1.
 
 Parity: pinned by tests/test_oracle_rigid.py (R A P of the oracle operator equals the
 one-sided closed form; the translation block of M equals the two-sided surface average
@@ -43,16 +50,26 @@ B0 = np.array([1.5] * 3 + [3.0] * 3)
 S_DIAG = np.array([4.0 * math.pi] * 3 + [8.0 * math.pi / 3.0] * 3)
 
 
-def restrict(field, xhat, w):
-    """(6,) rigid coefficients (a, b) of one sphere's node field (P, 3)."""
-    a = (w[:, None] * field).sum(0) / (4.0 * math.pi)
-    b = (w[:, None] * np.cross(xhat, field)).sum(0) * (3.0 / (8.0 * math.pi))
-    return np.concatenate([a, b])
+def b0(a=1.0):
+    """R M0 P on a sphere of radius a."""
+    return np.array([1.5 / a] * 3 + [3.0 / a] * 3)
 
 
-def prolong(y, xhat):
-    """Node field (P, 3) of the rigid coefficients y = (a, b): a + b x x."""
-    return y[None, :3] + np.cross(y[None, 3:], xhat)
+def s_diag(a=1.0):
+    return np.array([4.0 * math.pi * a ** 2] * 3 + [8.0 * math.pi * a ** 4 / 3.0] * 3)
+
+
+def restrict(field, xhat, w, a=1.0):
+    """(6,) rigid coefficients (a, b) of one sphere's node field (P, 3); xhat the unit
+    offsets and w the unit-sphere weights, the sphere's radius a."""
+    v = (w[:, None] * field).sum(0) / (4.0 * math.pi)
+    b = (w[:, None] * np.cross(xhat, field)).sum(0) * (3.0 / (8.0 * math.pi * a))
+    return np.concatenate([v, b])
+
+
+def prolong(y, xhat, a=1.0):
+    """Node field (P, 3) of the rigid coefficients y = (a, b): a + b x (x - c)."""
+    return y[None, :3] + np.cross(y[None, 3:], a * xhat)
 
 
 def _cross_matrix(r):
@@ -60,19 +77,20 @@ def _cross_matrix(r):
     return np.array([[0.0, -z, y], [z, 0.0, -x], [-y, x, 0.0]])
 
 
-def mobility(centres, two_sided=True):
+def mobility(centres, two_sided=True, radii=None):
     """(6 n_b, 6 n_b) grand mobility: Rotne-Prager-Yamakawa (two_sided) or the one-sided
     surface average that equals the operator's own restriction."""
     nb = len(centres)
-    f = 2.0 if two_sided else 1.0
+    a = np.ones(nb) if radii is None else np.asarray(radii, dtype=np.float64)
     M = np.zeros((6 * nb, 6 * nb))
     I3 = np.eye(3)
     for i in range(nb):
-        M[6 * i:6 * i + 3, 6 * i:6 * i + 3] = I3 / (6.0 * math.pi)
-        M[6 * i + 3:6 * i + 6, 6 * i + 3:6 * i + 6] = I3 / (8.0 * math.pi)
+        M[6 * i:6 * i + 3, 6 * i:6 * i + 3] = I3 / (6.0 * math.pi * a[i])
+        M[6 * i + 3:6 * i + 6, 6 * i + 3:6 * i + 6] = I3 / (8.0 * math.pi * a[i] ** 3)
         for k in range(nb):
             if k == i:
                 continue
+            f = a[i] ** 2 + a[k] ** 2 if two_sided else a[i] ** 2
             r = centres[i] - centres[k]
             d = np.linalg.norm(r)
             e = r / d
@@ -87,10 +105,11 @@ def mobility(centres, two_sided=True):
     return M
 
 
-def coarse_operator(centres, two_sided=True):
+def coarse_operator(centres, two_sided=True, radii=None):
     """A_c = M S: rigid coefficients of every sphere -> rigid part of the response."""
     nb = len(centres)
-    return mobility(centres, two_sided) * np.tile(S_DIAG, nb)[None, :]
+    a = np.ones(nb) if radii is None else np.asarray(radii, dtype=np.float64)
+    return mobility(centres, two_sided, a) * np.concatenate([s_diag(x) for x in a])[None, :]
 
 
 def correct(geom, r, z0):
@@ -98,11 +117,12 @@ def correct(geom, r, z0):
     xh = geom.grid["xhat"]
     w = geom.grid["wnode"]
     nb = geom.nb
-    xi = np.concatenate([restrict(r[geom.sphere_nodes(k)], xh, w) for k in range(nb)])
-    zeta = np.concatenate([restrict(z0[geom.sphere_nodes(k)], xh, w) for k in range(nb)])
-    y = np.linalg.solve(coarse_operator(geom.centres), xi)
+    a = geom.radii
+    xi = np.concatenate([restrict(r[geom.sphere_nodes(k)], xh, w, a[k]) for k in range(nb)])
+    zeta = np.concatenate([restrict(z0[geom.sphere_nodes(k)], xh, w, a[k]) for k in range(nb)])
+    y = np.linalg.solve(coarse_operator(geom.centres, radii=a), xi)
     d = (y - zeta).reshape(nb, 6)
     out = z0.copy()
     for k in range(nb):
-        out[geom.sphere_nodes(k)] += prolong(d[k], xh)
+        out[geom.sphere_nodes(k)] += prolong(d[k], xh, a[k])
     return out

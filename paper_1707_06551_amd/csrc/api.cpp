@@ -223,8 +223,8 @@ void apply_precond(bie_ctx* c, int op_base, int precision, int precond, const do
   const int64_t n = 3 * c->N + (op_base == BIE_OP_MOBILITY ? 6 * c->nb : 0);
   const bool rigid = (precond & BIE_PC_RIGID) != 0;
   const int base = precond & ~BIE_PC_RIGID;
-  if (c->poly && (precond & ~BIE_PC_M0) != 0)
-    throw Error{BIE_EINVAL, "spheres of several radii: preconditioners BIE_PC_NONE and BIE_PC_M0 only"};
+  if (c->poly && base == BIE_PC_MLP)
+    throw Error{BIE_EINVAL, "spheres of several radii: the learned correction is trained for unit spheres"};
   if (rigid && base == BIE_PC_NONE) throw Error{BIE_EINVAL, "BIE_PC_RIGID needs BIE_PC_M0 or BIE_PC_MLP"};
   if (rigid && c->nb > RIGID_MAX_SPHERES) throw Error{BIE_EINVAL, "BIE_PC_RIGID: too many spheres for the coarse solve"};
   switch (base) {
@@ -521,12 +521,11 @@ int bie_solve_mobility_traction(bie_ctx* c, const double* F, const double* T, co
     bie::rigid_restrict(c, rhs.as<double>(), ab.as<double>());
     BIE_HIP(hipMemcpyAsync(h.data(), ab.ptr, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     BIE_HIP(hipStreamSynchronize(c->stream));
-    // the restriction works on unit offsets and weights: (1/4pi) sum w u is already the
-    // mean velocity, (3/8pi) sum w o x u carries a^3 / a^4 too few powers of a: divide by a
+    // rigid_restrict returns the mean velocity and rotation of u on each sphere
     for (int64_t k = 0; k < nb; ++k)
       for (int d = 0; d < 3; ++d) {
         v[3 * k + d] = h[6 * k + d];
-        omega[3 * k + d] = h[6 * k + 3 + d] / c->radius[k];
+        omega[3 * k + d] = h[6 * k + 3 + d];
       }
     rho.release();
     rhs.release();

@@ -181,7 +181,8 @@ void coarse_correct(bie_ctx* c, const double* r, double* z);
 // global rigid-mode coarse correction: z <- z + P (A_c^-1 R r - R z)
 constexpr int64_t RIGID_MAX_SPHERES = 65536;
 void rigid_correct(bie_ctx* c, const double* r, double* z);
-// xi[6k..6k+5] = ((1/4pi) int_k f, (3/8pi) int_k (x - c_k) x f): rigid motion of a field
+// xi[6k..6k+5] = mean velocity and rotation of f on sphere k: (int f / (4 pi a^2),
+// 3 int (x - c) x f / (8 pi a^4)) (a = 1 for unit spheres)
 void rigid_restrict(bie_ctx* c, const double* f, double* xi);
 
 // single-layer traction K on the near pairs; u += a_k + b_k x (x - c_k) (ab = nb x 6)

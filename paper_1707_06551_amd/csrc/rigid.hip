@@ -19,6 +19,12 @@
 // Jacobi-preconditioned conjugate gradients with a matrix-free all-pairs product over the
 // sphere centres, in float64, on the device; scalars stay on the device and the host
 // reads the residual history every CHECK iterations.
+//
+// Spheres of radius a_k (rad != null): R f = (int f / (4 pi a^2), 3 int (x - c) x f /
+// (8 pi a^4)), P (a, b) = a + b x (x - c), S = diag(4 pi a^2, 8 pi a^4 / 3), and M the
+// polydisperse Rotne-Prager-Yamakawa mobility: self blocks 1/(6 pi a), 1/(8 pi a^3), the
+// translation-translation pair block with (a_i^2 + a_k^2) in place of 2, the rotation
+// blocks unchanged.  Without radii every a is 1 and these are the formulas above.
 #include <algorithm>
 
 #include "bie_internal.h"
@@ -47,9 +53,10 @@ __device__ inline double block_sum256(double v, double* lds) {
   return lds[0] + lds[1] + lds[2] + lds[3];
 }
 
-// xi[6k..6k+5] = R f on sphere k; one work-group per sphere.
+// xi[6k..6k+5] = R f on sphere k; one work-group per sphere.  With unit weights and
+// offsets: the mean is (1/4pi) sum w f for any radius, the rotation (3/(8 pi a)) sum w o x f.
 __global__ __launch_bounds__(256) void k_rigid_restrict(const double* f, const double* frame, const double* wnode,
-                                                       int P, double* xi) {
+                                                       int P, double* xi, const double* rad) {
   __shared__ double lds[4];
   const int64_t k = blockIdx.x;
   double acc[6] = {0, 0, 0, 0, 0, 0};
@@ -64,19 +71,21 @@ __global__ __launch_bounds__(256) void k_rigid_restrict(const double* f, const d
     acc[4] += w * (o[2] * v[0] - o[0] * v[2]);
     acc[5] += w * (o[0] * v[1] - o[1] * v[0]);
   }
+  const double a = rad ? rad[k] : 1.0;
   for (int d = 0; d < 6; ++d) {
     const double s = block_sum256(acc[d], lds);
-    if (threadIdx.x == 0) xi[6 * k + d] = s * (d < 3 ? 1.0 / (4.0 * M_PI) : 3.0 / (8.0 * M_PI));
+    if (threadIdx.x == 0) xi[6 * k + d] = s * (d < 3 ? 1.0 / (4.0 * M_PI) : 3.0 / (8.0 * M_PI * a));
   }
 }
 
 // z += P (y - zeta) at every node.
 __global__ void k_rigid_prolong(const double* y, const double* zeta, const double* frame, int P, int64_t N,
-                                double* z) {
+                                double* z, const double* rad) {
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < N; g += (int64_t)gridDim.x * blockDim.x) {
     const int64_t k = g / P;
     const int li = (int)(g - k * P);
-    const double* o = frame + 9 * li;
+    const double a = rad ? rad[k] : 1.0;
+    const double o[3] = {a * frame[9 * li], a * frame[9 * li + 1], a * frame[9 * li + 2]};   // x - c
     double d[6];
     for (int e = 0; e < 6; ++e) d[e] = y[6 * k + e] - zeta[6 * k + e];
     z[3 * g + 0] += d[0] + (d[4] * o[2] - d[5] * o[1]);
@@ -89,8 +98,8 @@ __global__ void k_rigid_prolong(const double* y, const double* zeta, const doubl
 // M the Rotne-Prager-Yamakawa mobility (self block included when s = i).  64 targets
 // per work-group (one per lane), the four waves take every fourth source.
 __global__ __launch_bounds__(256) void k_rpy_matvec(const double* centres4, const double* u, int64_t nb,
-                                                   double* partial) {
-  __shared__ double sc[RG_SRC][3];
+                                                   double* partial, const double* rad) {
+  __shared__ double sc[RG_SRC][4];   // centre, radius^2
   __shared__ double su[RG_SRC][6];
   __shared__ double red[3][64][6];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -98,6 +107,8 @@ __global__ __launch_bounds__(256) void k_rpy_matvec(const double* centres4, cons
   const int ns = (int)min<int64_t>(RG_SRC, nb - s0);
   for (int e = threadIdx.x; e < ns; e += 256) {
     for (int d = 0; d < 3; ++d) sc[e][d] = centres4[4 * (s0 + e) + d];
+    const double as = rad ? rad[s0 + e] : 1.0;
+    sc[e][3] = as * as;
     for (int d = 0; d < 6; ++d) su[e][d] = u[6 * (s0 + e) + d];
   }
   __syncthreads();
@@ -105,18 +116,20 @@ __global__ __launch_bounds__(256) void k_rpy_matvec(const double* centres4, cons
   const bool valid = i < nb;
   const int64_t ii = valid ? i : 0;
   const double cx = centres4[4 * ii], cy = centres4[4 * ii + 1], cz = centres4[4 * ii + 2];
+  const double ai = rad ? rad[ii] : 1.0;
   const double k8 = 1.0 / (8.0 * M_PI), k16 = 1.0 / (16.0 * M_PI);
   double a[6] = {0, 0, 0, 0, 0, 0};
   for (int e = wv; e < ns; e += 4) {
     const double Fx = su[e][0], Fy = su[e][1], Fz = su[e][2];
     const double Tx = su[e][3], Ty = su[e][4], Tz = su[e][5];
     if (s0 + e == ii) {
-      a[0] += Fx / (6.0 * M_PI);
-      a[1] += Fy / (6.0 * M_PI);
-      a[2] += Fz / (6.0 * M_PI);
-      a[3] += Tx * k8;
-      a[4] += Ty * k8;
-      a[5] += Tz * k8;
+      const double ft = 1.0 / (6.0 * M_PI * ai), fr = k8 / (ai * ai * ai);
+      a[0] += Fx * ft;
+      a[1] += Fy * ft;
+      a[2] += Fz * ft;
+      a[3] += Tx * fr;
+      a[4] += Ty * fr;
+      a[5] += Tz * fr;
       continue;
     }
     const double rx = cx - sc[e][0], ry = cy - sc[e][1], rz = cz - sc[e][2];
@@ -125,9 +138,11 @@ __global__ __launch_bounds__(256) void k_rpy_matvec(const double* centres4, cons
     const double id2 = id * id, id3 = id2 * id;
     const double rF = rx * Fx + ry * Fy + rz * Fz;
     const double rT = rx * Tx + ry * Ty + rz * Tz;
-    // translation: (1/8pi)[(1/d + 2/(3d^3)) F + (1/d - 2/d^3)(e.F) e - (r x T)/d^3]
-    const double c1 = id + (2.0 / 3.0) * id3;
-    const double c2 = (id - 2.0 * id3) * id2 * rF;
+    // translation: (1/8pi)[(1/d + s/(3d^3)) F + (1/d - s/d^3)(e.F) e - (r x T)/d^3],
+    // s = a_i^2 + a_k^2 (2 for unit spheres)
+    const double s2 = ai * ai + sc[e][3];
+    const double c1 = id + (s2 / 3.0) * id3;
+    const double c2 = (id - s2 * id3) * id2 * rF;
     a[0] += k8 * (c1 * Fx + c2 * rx - id3 * (ry * Tz - rz * Ty));
     a[1] += k8 * (c1 * Fy + c2 * ry - id3 * (rz * Tx - rx * Tz));
     a[2] += k8 * (c1 * Fz + c2 * rz - id3 * (rx * Ty - ry * Tx));
@@ -146,17 +161,20 @@ __global__ __launch_bounds__(256) void k_rpy_matvec(const double* centres4, cons
   }
 }
 
-// Jacobi scaling: diagonal of M^-1 (6 pi on forces, 8 pi on torques).
-__device__ inline double jacobi(int64_t e) { return (e % 6) < 3 ? 6.0 * M_PI : 8.0 * M_PI; }
+// Jacobi scaling: diagonal of M^-1 (6 pi a on forces, 8 pi a^3 on torques).
+__device__ inline double jacobi(int64_t e, const double* rad) {
+  const double a = rad ? rad[e / 6] : 1.0;
+  return (e % 6) < 3 ? 6.0 * M_PI * a : 8.0 * M_PI * a * a * a;
+}
 
 // CG start: x = 0, r = b, z = D r, p = z; block partial sums of r.z and r.r.
 __global__ __launch_bounds__(256) void k_cg_start(const double* b, int64_t n, double* x, double* r, double* z,
-                                                 double* p, double* dots) {
+                                                 double* p, double* dots, const double* rad) {
   __shared__ double lds[4];
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   double rz = 0, rr = 0;
   if (e < n) {
-    const double rv = b[e], zv = jacobi(e) * rv;
+    const double rv = b[e], zv = jacobi(e, rad) * rv;
     x[e] = 0.0;
     r[e] = rv;
     z[e] = zv;
@@ -216,7 +234,7 @@ __global__ __launch_bounds__(256) void k_cg_q(const double* partial, int nsplit,
 // alpha = rz / pq; x += alpha p; r -= alpha q; z = D r; block partials of r.z, r.r.
 __global__ __launch_bounds__(256) void k_cg_xr(const double* dots_pq, int nblk, const double* hist, int it, int64_t n,
                                               const double* p, const double* q, double* x, double* r, double* z,
-                                              double* dots) {
+                                              double* dots, const double* rad) {
   __shared__ double lds[4];
   double pq, unused;
   sum_pairs(dots_pq, nblk, lds, pq, unused);
@@ -226,7 +244,7 @@ __global__ __launch_bounds__(256) void k_cg_xr(const double* dots_pq, int nblk, 
   if (e < n) {
     x[e] += alpha * p[e];
     const double rv = r[e] - alpha * q[e];
-    const double zv = jacobi(e) * rv;
+    const double zv = jacobi(e, rad) * rv;
     r[e] = rv;
     z[e] = zv;
     rz = rv * zv;
@@ -256,17 +274,21 @@ __global__ __launch_bounds__(256) void k_cg_p(const double* dots, int nblk, doub
   }
 }
 
-// y = S^-1 x: forces -> a = F / 4 pi, torques -> b = 3 T / 8 pi.
-__global__ void k_unscale(const double* x, int64_t n, double* y) {
+// y = S^-1 x: forces -> a = F / (4 pi a^2), torques -> b = 3 T / (8 pi a^4).
+__global__ void k_unscale(const double* x, int64_t n, double* y, const double* rad) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) y[e] = x[e] * ((e % 6) < 3 ? 1.0 / (4.0 * M_PI) : 3.0 / (8.0 * M_PI));
+  if (e < n) {
+    const double a = rad ? rad[e / 6] : 1.0;
+    const double a2 = a * a;
+    y[e] = x[e] * ((e % 6) < 3 ? 1.0 / (4.0 * M_PI * a2) : 3.0 / (8.0 * M_PI * a2 * a2));
+  }
 }
 
 }  // namespace
 
 void rigid_restrict(bie_ctx* c, const double* f, double* xi) {
-  k_rigid_restrict<<<dim3((unsigned)c->nb), dim3(256), 0, c->stream>>>(f, c->frame.as<double>(),
-                                                                      c->wnode.as<double>(), c->P, xi);
+  k_rigid_restrict<<<dim3((unsigned)c->nb), dim3(256), 0, c->stream>>>(
+      f, c->frame.as<double>(), c->wnode.as<double>(), c->P, xi, c->poly ? c->radius_d.as<double>() : nullptr);
   BIE_HIP(hipGetLastError());
 }
 
@@ -296,9 +318,10 @@ void rigid_correct(bie_ctx* c, const double* r, double* z) {
   const double* wnode = c->wnode.as<double>();
   hipStream_t st = c->stream;
 
-  k_rigid_restrict<<<dim3((unsigned)nb), dim3(256), 0, st>>>(r, frame, wnode, c->P, xi);
-  k_rigid_restrict<<<dim3((unsigned)nb), dim3(256), 0, st>>>(z, frame, wnode, c->P, zeta);
-  k_cg_start<<<dim3(nblk), dim3(256), 0, st>>>(xi, n, x, rr, zz, pp, dots);
+  const double* rad = c->poly ? c->radius_d.as<double>() : nullptr;
+  k_rigid_restrict<<<dim3((unsigned)nb), dim3(256), 0, st>>>(r, frame, wnode, c->P, xi, rad);
+  k_rigid_restrict<<<dim3((unsigned)nb), dim3(256), 0, st>>>(z, frame, wnode, c->P, zeta, rad);
+  k_cg_start<<<dim3(nblk), dim3(256), 0, st>>>(xi, n, x, rr, zz, pp, dots, rad);
   k_cg_record<<<dim3(1), dim3(256), 0, st>>>(dots, nblk, hist);
   BIE_HIP(hipGetLastError());
   double h0[2];
@@ -311,9 +334,9 @@ void rigid_correct(bie_ctx* c, const double* r, double* z) {
       const int upto = std::min(RG_MAXIT, it + RG_CHECK);
       for (; it < upto; ++it) {
         k_rpy_matvec<<<dim3((unsigned)((nb + 63) / 64), (unsigned)nsplit), dim3(256), 0, st>>>(
-            c->centres4.as<double>(), pp, nb, c->rg_partial.as<double>());
+            c->centres4.as<double>(), pp, nb, c->rg_partial.as<double>(), rad);
         k_cg_q<<<dim3(nblk), dim3(256), 0, st>>>(c->rg_partial.as<double>(), nsplit, n, pp, qq, dots);
-        k_cg_xr<<<dim3(nblk), dim3(256), 0, st>>>(dots, nblk, hist, it, n, pp, qq, x, rr, zz, dots2);
+        k_cg_xr<<<dim3(nblk), dim3(256), 0, st>>>(dots, nblk, hist, it, n, pp, qq, x, rr, zz, dots2, rad);
         k_cg_p<<<dim3(nblk), dim3(256), 0, st>>>(dots2, nblk, hist, it, n, zz, pp);
       }
       BIE_HIP(hipGetLastError());
@@ -325,10 +348,10 @@ void rigid_correct(bie_ctx* c, const double* r, double* z) {
     }
   }
   c->rg_last_iters = it;
-  k_unscale<<<dim3(nblk), dim3(256), 0, st>>>(x, n, y);
+  k_unscale<<<dim3(nblk), dim3(256), 0, st>>>(x, n, y, rad);
   const int64_t N = c->N;
   const int pblocks = (int)std::min<int64_t>((N + 255) / 256, 8192);
-  k_rigid_prolong<<<dim3(pblocks), dim3(256), 0, st>>>(y, zeta, frame, c->P, N, z);
+  k_rigid_prolong<<<dim3(pblocks), dim3(256), 0, st>>>(y, zeta, frame, c->P, N, z, rad);
   BIE_HIP(hipGetLastError());
 }
 

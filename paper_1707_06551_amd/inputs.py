@@ -71,6 +71,33 @@ def place_spheres(n, box, min_gap, rng, max_tries=2_000_000):
     return out
 
 
+def place_spheres_radii(radii, box, min_gap, rng, max_tries=2_000_000):
+    """Random sequential addition of spheres of the given radii (largest first) in
+    [0, box]^3, each inside the box, with pairwise surface gap >= min_gap.  Returns the
+    centres in the order of `radii`."""
+    radii = np.asarray(radii, dtype=np.float64)
+    order = np.argsort(-radii, kind="stable")
+    out = np.empty((len(radii), 3))
+    placed = []
+    tries = 0
+    for idx in order:
+        a = radii[idx]
+        while True:
+            tries += 1
+            if tries > max_tries:
+                raise RuntimeError(f"placement stalled after {len(placed)} of {len(radii)} spheres")
+            cand = a + (box - 2 * a) * rng.random(3)
+            if placed:
+                pc = out[placed]
+                gap = np.linalg.norm(pc - cand[None, :], axis=1) - radii[placed] - a
+                if gap.min() < min_gap:
+                    continue
+            out[idx] = cand
+            placed.append(idx)
+            break
+    return out
+
+
 def make_workload(name, seed=0):
     """Centres and right-hand-side data of a named workload.
 

@@ -253,6 +253,57 @@ def test_fluid_points_match_oracle(cluster, opname):
     assert rel_err(out, ref) < 1e-11, (rel_err(out, ref), max_rel(out, ref))
 
 
+def test_rigid_coarse_correction_with_radii(cluster):
+    # the global rigid-mode correction (polydisperse Rotne-Prager-Yamakawa coarse
+    # operator) against the oracle's dense coarse solve, its no-op on isolated spheres,
+    # and the resistance solve it preconditions
+    from oracle import rigid
+    from oracle.precond import m0_resistance
+    from paper_1707_06551_amd import bie
+    c, a, s, g = cluster
+    r = np.random.default_rng(17).standard_normal((g.N, 3))
+    z = host(s.apply_precond(bie.OP_DN_BIE, dev(r), precond=bie.PC_M0 | bie.PC_RIGID)).reshape(g.N, 3)
+    ref = rigid.correct(g, r, m0_resistance(g, r))
+    assert rel_err(z, ref) < 1e-6, rel_err(z, ref)   # coarse CG to relative residual 1e-7
+    z0 = host(s.apply_precond(bie.OP_DN_BIE, dev(r), precond=bie.PC_M0)).reshape(g.N, 3)
+    assert rel_err(z, z0) > 1e-3
+    for rad in (0.4, 2.5):
+        s1 = bie.Spheres(np.array([[0.2, 0.1, -0.3]]), 6, radii=[rad])
+        y = dev(np.random.default_rng(18).standard_normal(3 * s1.N))
+        z1 = host(s1.apply_precond(bie.OP_DN_BIE, y, precond=bie.PC_M0 | bie.PC_RIGID))
+        z2 = host(s1.apply_precond(bie.OP_DN_BIE, y, precond=bie.PC_M0))
+        assert max_rel(z1, z2) < 1e-12, rad
+        s1.close()
+    rng = np.random.default_rng(19)
+    v = rng.standard_normal((g.nb, 3))
+    om = rng.standard_normal((g.nb, 3))
+    F0, T0, _p, i0 = s.solve_resistance(v, om, tol=1e-11, precond=bie.PC_M0)
+    F1, T1, _p, i1 = s.solve_resistance(v, om, tol=1e-11, precond=bie.PC_M0 | bie.PC_RIGID)
+    assert i0["converged"] and i1["converged"]
+    assert rel_err(F1, F0) < 1e-8 and rel_err(T1, T0) < 1e-8
+    print(f"polydisperse resistance, 6 spheres: M0 {i0['iters']} its, M0 + rigid {i1['iters']} its")
+
+
+def test_rigid_correction_gain_on_a_polydisperse_suspension():
+    # 200 spheres of radii 0.5 and 1 (random sequential addition, gaps >= 0.1), p = 4:
+    # the resistance form under M0 needs many more iterations than with the correction
+    from paper_1707_06551_amd import bie
+    from paper_1707_06551_amd.inputs import place_spheres_radii
+    rng = np.random.default_rng(20)
+    radii = np.where(rng.random(200) < 0.5, 0.5, 1.0)
+    c = place_spheres_radii(radii, 16.0, 0.1, rng)
+    s = bie.Spheres(c, 4, near_gap=1.0, radii=radii)
+    v = rng.standard_normal((200, 3))
+    om = rng.standard_normal((200, 3))
+    F0, T0, _p, i0 = s.solve_resistance(v, om, tol=1e-8, precision=bie.MIXED, precond=bie.PC_M0)
+    F1, T1, _p, i1 = s.solve_resistance(v, om, tol=1e-8, precision=bie.MIXED, precond=bie.PC_M0 | bie.PC_RIGID)
+    print(f"200 polydisperse spheres, p = 4: M0 {i0['iters']} its, M0 + rigid {i1['iters']} its")
+    assert i0["converged"] and i1["converged"]
+    assert rel_err(F1, F0) < 1e-6 and rel_err(T1, T0) < 1e-6
+    assert i1["iters"] < 0.7 * i0["iters"], (i0["iters"], i1["iters"])
+    s.close()
+
+
 def test_porous_media_solve_matches_oracle(cluster):
     # Problem 1: spheres held fixed in a uniform stream U, (1/2 + S + D) mu = -U
     from paper_1707_06551_amd import bie
@@ -288,8 +339,6 @@ def test_polydisperse_rejects_unit_only_features(cluster):
     mu = dev(np.zeros(3 * g.N))
     with pytest.raises(bie.BieError):
         s.solve_magnetic([0.0, 0.0, 1.0], 0.5)
-    with pytest.raises(bie.BieError):
-        s.solve_resistance(np.zeros((g.nb, 3)), np.ones((g.nb, 3)), precond=bie.PC_M0 | bie.PC_RIGID)
     with pytest.raises(bie.BieError):
         s.apply_precond(bie.OP_SD_BIE, mu, precond=bie.PC_MLP)
     with pytest.raises(bie.BieError):

@@ -227,3 +227,58 @@ def test_fluid_points_around_a_fixed_sphere_of_radius_a():
                                                                                           - 3 * rU * r / dd ** 5)
     err = np.abs(u - ref).max(axis=1)
     assert err[:3].max() < 1e-12 and err[3:].max() < 3e-7 and err[4:].max() < 1e-12, err
+
+
+def test_rigid_coarse_operator_with_radii():
+    # R A P of the completed operator (radii) = the one-sided closed form; the two-sided
+    # (polydisperse Rotne-Prager-Yamakawa) translation block = the Stokeslet averaged over
+    # both spheres (quadrature); R M0 P = diag(3/(2a), 3/a) = A_c^-1 of one sphere
+    from oracle import rigid
+    from oracle.kernels import kernel_block
+    from oracle.precond import m0_resistance
+    c = np.array([[0.0, 0.0, 0.0], [2.9, 0.4, 0.2], [0.3, -2.9, 1.5]])
+    a = np.array([1.0, 0.6, 0.8])
+    g = Geometry(c, 10, near_gap=1.0, radii=a)
+    assert g.near.sum() == 0
+    ops = Operators(g)
+    xh, w = g.grid["xhat"], g.grid["wnode"]
+    cols = []
+    for k in range(g.nb):
+        for m in range(6):
+            y = np.zeros(6)
+            y[m] = 1.0
+            f = np.zeros((g.N, 3))
+            f[g.sphere_nodes(k)] = rigid.prolong(y, xh, a[k])
+            u = ops.apply("DN_BIE", f)
+            cols.append(np.concatenate([rigid.restrict(u[g.sphere_nodes(i)], xh, w, a[i]) for i in range(g.nb)]))
+    rap = np.array(cols).T
+    one = rigid.coarse_operator(c, two_sided=False, radii=a)
+    assert np.abs(rap - one).max() < 1e-7 * np.abs(one).max()
+    # two-sided translation block by quadrature over spheres of radii 0.7 and 0.4
+    g24 = Geometry(np.zeros((1, 3)), 24, near_gap=1.0)
+    xh24, w24 = g24.grid["xhat"], g24.grid["wnode"]
+    e = np.array([0.36, -0.48, 0.8])
+    ai, ak, d = 0.7, 0.4, 1.6
+    K = kernel_block(d * e + ai * xh24, ak * xh24, xh24, 1.0, 0.0)
+    avg = np.einsum("t,tisj,s->ij", w24, K, w24) / (4 * math.pi) ** 2
+    M = rigid.mobility(np.stack([d * e, np.zeros(3)]), radii=[ai, ak])
+    assert np.abs(M[0:3, 6:9] - avg).max() < 1e-10
+    # isolated sphere of radius a
+    for rad in (0.4, 2.0):
+        g1 = Geometry(np.zeros((1, 3)), 8, near_gap=1.0, radii=[rad])
+        y = np.random.default_rng(12).standard_normal(6)
+        f = rigid.prolong(y, g1.grid["xhat"], rad)
+        assert np.abs(rigid.restrict(f, g1.grid["xhat"], g1.grid["wnode"], rad) - y).max() < 1e-13
+        z = m0_resistance(g1, f)
+        assert np.abs(rigid.restrict(z, g1.grid["xhat"], g1.grid["wnode"], rad) - rigid.b0(rad) * y).max() < 1e-12
+        Ac = rigid.coarse_operator(np.zeros((1, 3)), radii=[rad])
+        assert np.abs(np.linalg.inv(Ac) - np.diag(rigid.b0(rad))).max() < 1e-12 * rigid.b0(rad).max()
+        r = np.random.default_rng(13).standard_normal((g1.N, 3))
+        z0 = m0_resistance(g1, r)
+        assert np.abs(rigid.correct(g1, r, z0) - z0).max() < 1e-12
+
+
+def test_polydisperse_rpy_is_positive_definite():
+    from oracle import rigid
+    c, a = poly_cluster()
+    assert np.linalg.eigvalsh(rigid.mobility(c, radii=a)).min() > 0
