@@ -75,6 +75,7 @@ struct bie_ctx {
   int nwords = 0;
   bie::DevBuf dnear_ptr, dnear_idx;
   bie::DevBuf otab, otab_f;    // P x 4 unit offsets of the nodes of a sphere (double / float)
+  bie::DevBuf osrc, osrc_f;    // P x 4 the same offsets times -2 (far-field source table)
   bie::DevBuf frame;           // P x 9 double: e_r, e_theta, e_phi at each node
   bie::DevBuf wnode;           // P double: quadrature weight of each node of a sphere
   // device: transform tables, double and float copies

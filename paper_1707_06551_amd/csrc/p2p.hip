@@ -13,14 +13,16 @@
 // (formed from the float64 centre difference plus the target's own offset, so float32
 // keeps full relative accuracy at any box size).  A source node y = c + o has
 // r = x - y = p - o, and because |o| = 1:
-//   d = p . o,  r.r = (|p|^2 + 1) - 2 d,  r.n_y = r.o = d - 1,  r.q = p.q - o.q.
-// The sums over a source sphere are kept as  C = sum c_y,  Co = sum c_y o_y,  Q = sum q_y / r
-// so that  sum c_y r_y = p C - Co.  For the allowed (far) pairs r >= d* so the
+//   r.r = (|p|^2 + 1) - 2 p.o,  r.n_y = r.o = p.o - 1,  r.q = p.q - o.q.
+// The source table holds o~ = -2 o (an exact scaling), so that r.r = K + p.o~ with
+// K = |p|^2 + 1 is one chain of three fused multiply-adds started from K.
+// The sums over a source sphere are kept as  C = sum c_y,  Co~ = sum c_y o~_y,  Q = sum q_y / r
+// so that  sum c_y r_y = p C + Co~ / 2.  For the allowed (far) pairs r >= d* so the
 // cancellation in r.r costs a few ulp at most.  For S+D the double-layer factor
-// 1 + 6 (r.n)/r^2 is rewritten with r.n = d - 1 = (|p|^2 - 1 - r.r)/2 as
+// 1 + 6 (r.n)/r^2 is rewritten with r.n = (|p|^2 - 1 - r.r)/2 as
 // 3 (|p|^2 - 1)/r^2 - 2, one fused multiply-add per pair with 3 (|p|^2 - 1) formed once
 // per (target, source sphere); the factor stays near 1 (|p| <= r + 1), so this costs no
-// cancellation.  Per pair: S+D 19 VALU + 1 rsqrt, D 17, S 17.  All inner-loop operands
+// cancellation.  Per pair: S+D 18 VALU + 1 rsqrt, D 17, S 16, K 17.  All inner-loop operands
 // are VGPRs, literals or inline constants: on gfx950 a float32 VALU instruction with an
 // SGPR operand issues at half the rate of one without (measured), which is why float32
 // sources are staged in LDS rather than read through the scalar cache.  Self and near source spheres are skipped through a per-target bit mask (a whole
@@ -34,7 +36,8 @@ namespace bie {
 
 struct FarParams {
   const void* q;          // N x 4 (R): w * mu, w * (o . mu)
-  const void* otab;       // P x 4 (R): unit offsets of the nodes of a sphere
+  const void* otab;       // P x 4 (R): unit offsets of the nodes of a sphere (targets)
+  const void* osrc;       // P x 4 (R): the same offsets times -2 (sources)
   const double* centres4; // nb x 4
   const uint32_t* excl;   // nb x nwords
   const double* moments;  // nb x 6 (completion only)
@@ -69,17 +72,24 @@ struct R4 {
 // KIND: 1 = Stokeslet, 2 = double layer, 3 = Stokeslet + double layer, 4 = single-layer
 // traction K (Eq. 2.22, normal of the TARGET node).  Constants:
 //   S:   (1/8pi) [q/r + r (r.q)/r^3]            -> c = (r.q) / r^3
-//   D:   (3/4pi) r (r.q)(r.n)/r^5               -> c = (r.q)(r.n) / r^5
+//   D:   (3/4pi) r (r.q)(r.n)/r^5               -> c = (r.q)(r.n) / r^5, r.n = -(p.o~)/2 - 1
 //   S+D: (1/8pi) [q/r + r (r.q)/r^3 (1 + 6 (r.n)/r^2)]  -> c = (r.q)/r^3 (3 (|p|^2 - 1)/r^2 - 2)
 //   K:   -(3/4pi) r (r.q)(r.n_x)/r^5            -> c = (r.q)(r.n_x) / r^5, with
-//        r.n_x = p.n_x - o.n_x and K3 = p.n_x formed once per (target, source sphere)
-// tc is -2 for unit spheres (a literal after inlining); a_s - 3 in units of a source
-// radius a_s (the single layer's share of t scales with a_s, the double layer's not).
+//        r.n_x = p.n_x - o.n_x = K3 + o~.(n_x / 2), K3 = p.n_x formed once per (target,
+//        source sphere) and tn = n_x / 2 per target
+// o holds o~ = -2 o.  tc is -2 for unit spheres (a literal after inlining); a_s - 3 in
+// units of a source radius a_s (the single layer's share of t scales with a_s, the double
+// layer's not).
 template <typename R, int KIND>
 __device__ __forceinline__ void pair(R px, R py, R pz, R K, R K3, R tnx, R tny, R tnz, R tc, const R4<R>& o,
                                      const R4<R>& q, R& C, R& Cx, R& Cy, R& Cz, R& Qx, R& Qy, R& Qz) {
-  const R d = fma(pz, o.z, fma(py, o.y, px * o.x));
-  const R r2 = fma((R)-2, d, K);
+  R r2, d2 = 0;
+  if (KIND == 2) {
+    d2 = fma(pz, o.z, fma(py, o.y, px * o.x));   // -2 p.o
+    r2 = K + d2;
+  } else {
+    r2 = fma(pz, o.z, fma(py, o.y, fma(px, o.x, K)));
+  }
   const R ir = rsqrt_r<R>(r2);
   const R ir2 = ir * ir;
   const R rq = fma(pz, q.z, fma(py, q.y, fma(px, q.x, -q.w)));
@@ -87,10 +97,10 @@ __device__ __forceinline__ void pair(R px, R py, R pz, R K, R K3, R tnx, R tny, 
   if (KIND == 1) {
     c = rq * ir * ir2;
   } else if (KIND == 2) {
-    const R rn = d - (R)1;
+    const R rn = fma((R)-0.5, d2, (R)-1);
     c = (rq * rn) * (ir2 * ir2 * ir);
   } else if (KIND == 4) {
-    const R rn = K3 - fma(o.z, tnz, fma(o.y, tny, o.x * tnx));
+    const R rn = fma(o.z, tnz, fma(o.y, tny, fma(o.x, tnx, K3)));
     c = (rq * rn) * (ir2 * ir2 * ir);
   } else {
     const R t = fma(K3, ir2, tc);   // 1 + 6 (r.n)/r^2 with K3 = 3 (|p|^2 - 1), tc = -2
@@ -117,17 +127,19 @@ __device__ __forceinline__ void pair(R px, R py, R pz, R K, R K3, R tnx, R tny, 
 template <typename R, int KIND, int TPL, int SRC, bool RADII>
 __global__ __launch_bounds__(256) void far_kernel(FarParams a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  R4<R>* ot = reinterpret_cast<R4<R>*>(smem_raw);
-  R4<R>* qs = ot + a.P;
+  // source table interleaved in LDS: sm[2 i] = o~_i (the same for every sphere, loaded
+  // once), sm[2 i + 1] = q_i of the current sphere; one address serves both reads
+  R4<R>* sm = reinterpret_cast<R4<R>*>(smem_raw);
   const int tid = threadIdx.x;
   const int P = a.P;
   const R4<R>* qg = reinterpret_cast<const R4<R>*>(a.q);
   const R4<R>* og = reinterpret_cast<const R4<R>*>(a.otab);
+  const R4<R>* osg = reinterpret_cast<const R4<R>*>(a.osrc);
   typedef __attribute__((address_space(4))) const R4<R> CR4;
   const CR4* qc = (const CR4*)qg;
-  const CR4* oc = (const CR4*)og;
+  const CR4* oc = (const CR4*)osg;
   if (SRC == 0)
-    for (int i = tid; i < P; i += 256) ot[i] = og[i];
+    for (int i = tid; i < P; i += 256) sm[2 * i] = osg[i];
 
   const int s_begin = blockIdx.y * a.sph_per_split;
   const int s_end = (int)min<int64_t>(a.nb, (int64_t)s_begin + a.sph_per_split);
@@ -162,7 +174,7 @@ __global__ __launch_bounds__(256) void far_kernel(FarParams a) {
   for (int s = s_begin; s < s_end; ++s) {
     if (SRC == 0) {
       __syncthreads();
-      for (int i = tid; i < P; i += 256) qs[i] = qg[(int64_t)s * P + i];
+      for (int i = tid; i < P; i += 256) sm[2 * i + 1] = qg[(int64_t)s * P + i];
     }
     const double csx = a.centres4[4 * s], csy = a.centres4[4 * s + 1], csz = a.centres4[4 * s + 2];
     const double as = RADII ? a.radius[s] : 1.0;
@@ -223,8 +235,8 @@ __global__ __launch_bounds__(256) void far_kernel(FarParams a) {
     for (int i = 0; i < P; ++i) {
       R4<R> o, qq;
       if (SRC == 0) {
-        o = ot[i];
-        qq = qs[i];
+        o = sm[2 * i];
+        qq = sm[2 * i + 1];
       } else {
         const CR4& oo = oc[i];
         const CR4& q4 = qc[(int64_t)s * P + i];
@@ -233,21 +245,23 @@ __global__ __launch_bounds__(256) void far_kernel(FarParams a) {
       }
 #pragma unroll
       for (int k = 0; k < TPL; ++k)
-        pair<R, KIND>(px[k], py[k], pz[k], K[k], K3[k], oxt[k][0], oxt[k][1], oxt[k][2], tcv[k], o, qq, C[k], Cx[k],
-                      Cy[k], Cz[k], Qx[k], Qy[k], Qz[k]);
+        pair<R, KIND>(px[k], py[k], pz[k], K[k], K3[k], (R)0.5 * oxt[k][0], (R)0.5 * oxt[k][1], (R)0.5 * oxt[k][2],
+                      tcv[k], o, qq, C[k], Cx[k], Cy[k], Cz[k], Qx[k], Qy[k], Qz[k]);
     }
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
       if (skip[k]) continue;
-      R part[3] = {fma(px[k], C[k], Qx[k] - Cx[k]), fma(py[k], C[k], Qy[k] - Cy[k]), fma(pz[k], C[k], Qz[k] - Cz[k])};
+      // sum c r = p C + Co~ / 2
+      R part[3] = {fma(px[k], C[k], fma((R)0.5, Cx[k], Qx[k])), fma(py[k], C[k], fma((R)0.5, Cy[k], Qy[k])),
+                   fma(pz[k], C[k], fma((R)0.5, Cz[k], Qz[k]))};
       if (RADII && KIND == 1) {
         part[0] *= (R)as;
         part[1] *= (R)as;
         part[2] *= (R)as;
       } else if (RADII && KIND == 3) {
-        part[0] = fma(px[k], C[k], fma((R)as, Qx[k], -Cx[k]));
-        part[1] = fma(py[k], C[k], fma((R)as, Qy[k], -Cy[k]));
-        part[2] = fma(pz[k], C[k], fma((R)as, Qz[k], -Cz[k]));
+        part[0] = fma(px[k], C[k], fma((R)as, Qx[k], (R)0.5 * Cx[k]));
+        part[1] = fma(py[k], C[k], fma((R)as, Qy[k], (R)0.5 * Cy[k]));
+        part[2] = fma(pz[k], C[k], fma((R)as, Qz[k], (R)0.5 * Cz[k]));
       }
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -303,6 +317,7 @@ void launch_far(bie_ctx* c, int precision, const OpSpec& spec, double* u) {
   const bool f32 = precision == BIE_MIXED;
   a.q = c->q.ptr;
   a.otab = f32 ? c->otab_f.ptr : c->otab.ptr;
+  a.osrc = f32 ? c->osrc_f.ptr : c->osrc.ptr;
   a.centres4 = c->centres4.as<double>();
   a.excl = c->excl.as<uint32_t>();
   a.moments = c->moments.as<double>();

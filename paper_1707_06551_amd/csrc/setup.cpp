@@ -341,6 +341,8 @@ void build(bie_ctx* c, const double* centres, const double* radii, int64_t nb, c
   const int P = c->P;
   std::vector<double> otab(4 * P), frame(9 * P), wnode(P);
   std::vector<float> otab_f(4 * P);
+  std::vector<double> osrc(4 * P, 0.0);
+  std::vector<float> osrc_f(4 * P, 0.0f);
   for (int j = 0; j < c->nlat; ++j) {
     double tj = tt[j], sj = std::sqrt(std::max(0.0, 1.0 - tj * tj));
     for (int l = 0; l < nphi; ++l) {
@@ -350,6 +352,8 @@ void build(bie_ctx* c, const double* centres, const double* radii, int64_t nb, c
       for (int d = 0; d < 3; ++d) {
         otab[4 * g + d] = x[d];
         otab_f[4 * g + d] = (float)x[d];
+        osrc[4 * g + d] = -2.0 * x[d];   // exact: a power-of-two scaling
+        osrc_f[4 * g + d] = -2.0f * (float)x[d];
       }
       otab[4 * g + 3] = 0.0;
       otab_f[4 * g + 3] = 0.0f;
@@ -412,6 +416,8 @@ void build(bie_ctx* c, const double* centres, const double* radii, int64_t nb, c
   upload_vec(c->dnear_idx, c->near_idx.empty() ? std::vector<int>{0} : c->near_idx);
   upload_vec(c->otab, otab);
   upload_vec(c->otab_f, otab_f);
+  upload_vec(c->osrc, osrc);
+  upload_vec(c->osrc_f, osrc_f);
   upload_vec(c->frame, frame);
   upload_vec(c->wnode, wnode);
   upload_vec(c->leg, leg);
