@@ -88,6 +88,11 @@ typedef struct {
                         target grid, projected, rotated back and summed per target
                         before one inverse transform - the band-limited projection of
                         the near field instead of its nodal values                       */
+  int legendre_mfma; /* Legendre stages of the transforms (Section 2.1, Eqs. 2.9-2.14):
+                        0 = per-mode FMA loops from LDS, 1 = matrix cores (v_mfma 16x16x4
+                        in float32 / float64, one tile per order m and row block of 16).
+                        Same results up to rounding order; 0 is faster at every measured
+                        size (the stage is latency-bound).  0 or 1, BIE_EINVAL otherwise */
 } bie_opts;
 
 /* Builds the discretisation for n_spheres unit spheres (Eq. 4.2 grid, Legendre and

@@ -43,7 +43,8 @@ class MlpData(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int), ("n_phi", ctypes.c_int), ("near_gap", ctypes.c_double),
-                ("device", ctypes.c_int), ("hip_stream", ctypes.c_void_p), ("near_method", ctypes.c_int)]
+                ("device", ctypes.c_int), ("hip_stream", ctypes.c_void_p), ("near_method", ctypes.c_int),
+                ("legendre_mfma", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -210,9 +211,11 @@ def _dptr(t):
 
 class Spheres:
     """A context for n_b spheres (bie_build_spheres; bie_build_spheres_radii when radii
-    are given: polydisperse suspensions, a subset of the operators)."""
+    are given: polydisperse suspensions, a subset of the operators).  legendre_mfma = 1
+    runs the transforms' Legendre stages on the matrix cores (bie_opts.legendre_mfma)."""
 
-    def __init__(self, centres, p, n_phi=0, near_gap=1.0, device=0, stream=None, near_method=0, radii=None):
+    def __init__(self, centres, p, n_phi=0, near_gap=1.0, device=0, stream=None, near_method=0, radii=None,
+                 legendre_mfma=0):
         import torch
         L = lib()
         c = np.ascontiguousarray(centres, dtype=np.float64).reshape(-1, 3)
@@ -220,7 +223,7 @@ class Spheres:
             stream = torch.cuda.current_stream(device)
         self.stream = stream
         self.device = device
-        o = Opts(p, n_phi, near_gap, device, ctypes.c_void_p(stream.cuda_stream), near_method)
+        o = Opts(p, n_phi, near_gap, device, ctypes.c_void_p(stream.cuda_stream), near_method, legendre_mfma)
         h = ctypes.c_void_p()
         if radii is None:
             _check(L.bie_build_spheres(_hptr(c), c.shape[0], ctypes.byref(o), ctypes.byref(h)))

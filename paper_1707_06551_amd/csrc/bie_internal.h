@@ -115,6 +115,7 @@ struct bie_ctx {
 
   // near evaluation by pole rotation (near_rot.hip), near_method = 1
   int near_method = 0;
+  int legendre_mfma = 0;   // Legendre stages of the transforms on the matrix cores
   bie::DevBuf wig;                  // sum_n (2n+1)^2 complex: Wigner matrices of R_x(-pi/2)
   bie::DevBuf nearcoef;             // nb x 3 x ncoef x 2: summed near-field coefficients
   bie::DevBuf tlat_d;               // nlat cos(theta_j)

@@ -248,6 +248,8 @@ void build(bie_ctx* c, const double* centres, const double* radii, int64_t nb, c
   c->near_gap = o->near_gap > 0 ? o->near_gap : 1.0;
   if (o->near_method != 0 && o->near_method != 1) throw Error{BIE_EINVAL, "near_method must be 0 or 1"};
   c->near_method = o->near_method;
+  if (o->legendre_mfma != 0 && o->legendre_mfma != 1) throw Error{BIE_EINVAL, "legendre_mfma must be 0 or 1"};
+  c->legendre_mfma = o->legendre_mfma;
   c->device = o->device;
   c->stream = (hipStream_t)o->hip_stream;
   BIE_HIP(hipSetDevice(c->device));

@@ -9,6 +9,17 @@
 // Self term (Section 4.1, Eqs. 4.6-4.7): coefficients times the eigenvalues of Theorem 2
 // (double layer as principal value), then the inverse transform (Eqs. 2.15-2.17):
 // V, W, X -> (Y, G, X) coefficients -> Legendre synthesis per latitude -> inverse DFT.
+//
+// The Legendre stages are, per azimuthal order m, small dense contractions: projection
+// (rows n = m..p) x (latitudes j) x (Fourier columns), synthesis (latitudes) x (n) x
+// (coefficient columns).  They run either as per-mode FMA loops from LDS, or (MF, the
+// context's legendre_mfma option) on the matrix cores: one 16 x 16 tile per (m, row
+// block), K = 4 per instruction, the three tables (Pbar, dPbar, m Pbar / sin)
+// accumulated into one tile with their right-hand columns arranged so that the tile's
+// columns are the combinations the next step needs (see the comments at each stage).
+// Lane layout of v_mfma_{f32,f64}_16x16x4 (read off the hardware with known operands):
+// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; its four results are
+// D[4 (l / 16) + v][l % 16] for f32 and D[l / 16 + 4 v][l % 16] for f64, v = 0..3.
 #include "bie_internal.h"
 
 namespace bie {
@@ -40,12 +51,33 @@ struct VshParams {
   double lamS[3][33];
 };
 
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef double vd4 __attribute__((ext_vector_type(4)));
+template <typename R>
+struct Tile;
+template <>
+struct Tile<float> {
+  typedef vf4 T;
+  static __device__ __forceinline__ vf4 step(float a, float b, vf4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kq, int v) { return 4 * kq + v; }
+};
+template <>
+struct Tile<double> {
+  typedef vd4 T;
+  static __device__ __forceinline__ vd4 step(double a, double b, vd4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kq, int v) { return kq + 4 * v; }
+};
+
 __device__ inline double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
-template <typename R>
+template <typename R, bool MF>
 __global__ __launch_bounds__(256) void vsh_kernel(VshParams a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int k = blockIdx.x;
@@ -54,7 +86,9 @@ __global__ __launch_bounds__(256) void vsh_kernel(VshParams a) {
   R* fs = reinterpret_cast<R*>(smem_raw);   // 3 x P spherical components
   R* F = fs + 3 * P;                         // 3 x nl x M1 x 2 Fourier coefficients
   R* C = F + 3 * nl * M1 * 2;                // 3 x nc x 2 (Y, G, X) coefficients
-  double* red = reinterpret_cast<double*>(smem_raw + ((sizeof(R) * (3 * P + 3 * nl * M1 * 2 + 3 * nc * 2) + 15) & ~size_t(15)));
+  R* PJ = C + 3 * nc * 2;                    // nc x 6 projections (matrix-core path)
+  double* red = reinterpret_cast<double*>(smem_raw + ((sizeof(R) * (3 * P + 3 * nl * M1 * 2 + 12 * nc) + 15) & ~size_t(15)));
+  const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
   const R* leg = reinterpret_cast<const R*>(a.leg);
   const R* dft = reinterpret_cast<const R*>(a.dft);
   const R* wl = reinterpret_cast<const R*>(a.wlat);
@@ -95,7 +129,6 @@ __global__ __launch_bounds__(256) void vsh_kernel(VshParams a) {
       }
     }
     if (a.want_moments) {
-      const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
       for (int d = 0; d < 6; ++d) {
         double s = wave_sum(mom[d]);
         if (lane == 0) red[d * 4 + wv] = s;
@@ -131,32 +164,90 @@ __global__ __launch_bounds__(256) void vsh_kernel(VshParams a) {
     __syncthreads();
 
     // ---- Legendre projection onto V, W, X ------------------------------------------
+    // with b = int dPbar F_t-like sums and c = int m Pbar / sin sums (weights w_j):
+    //   g = b_t - i c_p,  x = b_p + i c_t,  a = int Pbar F_r
+    // V = (g - (n+1) a) / ((n+1)(2n+1)); W = (g + n a) / (n(2n+1)); X = x / (n(n+1))
+    if (MF) {
+      // tile rows n = m + 16 rt + (0..15), K = latitudes j, columns
+      //   0: Re g  1: Im g  2: Re x  3: Im x  4: Re a  5: Im a
+      // from dPbar x [Re F_t, Im F_t, Re F_p, Im F_p] + mQ x [Im F_p, -Re F_p, -Im F_t,
+      // Re F_t] + Pbar x [0, 0, 0, 0, Re F_r, Im F_r]
+      const int col = lane & 15, kq = lane >> 4;
+      for (int task = wv; task < 2 * M1; task += nw) {
+        const int m = task >> 1, rt = task & 1;
+        if (16 * rt >= a.p + 1 - m) continue;   // wave-uniform
+        const int off = m * (a.p + 1) - (m * (m - 1)) / 2;
+        const int nA = m + 16 * rt + col;
+        const bool rowok = nA <= a.p;
+        const int iA = off + (rowok ? nA - m : 0);
+        typename Tile<R>::T acc = {0, 0, 0, 0};
+        for (int ks = 0; ks < (nl + 3) / 4; ++ks) {
+          const int j = 4 * ks + kq;
+          const bool jok = j < nl;
+          const int jc = jok ? j : 0;
+          const R wj = (rowok && jok) ? wl[jc] : (R)0;
+          const R ap = wj * leg[((size_t)0 * nc + iA) * nl + jc];
+          const R ad = wj * leg[((size_t)1 * nc + iA) * nl + jc];
+          const R aq = wj * leg[((size_t)2 * nc + iA) * nl + jc];
+          const R jm = jok ? (R)1 : (R)0;
+          const R* Fr = F + ((0 * nl + jc) * M1 + m) * 2;
+          const R* Ft = F + ((1 * nl + jc) * M1 + m) * 2;
+          const R* Fp = F + ((2 * nl + jc) * M1 + m) * 2;
+          const R trr = jm * Ft[0], tri = jm * Ft[1], prr = jm * Fp[0], pri = jm * Fp[1];
+          const R bd = col == 0 ? trr : col == 1 ? tri : col == 2 ? prr : col == 3 ? pri : (R)0;
+          const R bq = col == 0 ? pri : col == 1 ? -prr : col == 2 ? -tri : col == 3 ? trr : (R)0;
+          const R bp = col == 4 ? jm * Fr[0] : col == 5 ? jm * Fr[1] : (R)0;
+          acc = Tile<R>::step(ad, bd, acc);
+          acc = Tile<R>::step(aq, bq, acc);
+          acc = Tile<R>::step(ap, bp, acc);
+        }
+        if (col < 6)
+          for (int v = 0; v < 4; ++v) {
+            const int nD = m + 16 * rt + Tile<R>::row(kq, v);
+            if (nD <= a.p) PJ[(off + nD - m) * 6 + col] = acc[v];
+          }
+      }
+      __syncthreads();
+    }
     for (int i = tid; i < nc; i += nt) {
       const int m = a.modes[2 * i], n = a.modes[2 * i + 1];
-      const R* Lp = leg + ((size_t)0 * nc + i) * nl;
-      const R* Ld = leg + ((size_t)1 * nc + i) * nl;
-      const R* Lq = leg + ((size_t)2 * nc + i) * nl;
-      R ar = 0, ai = 0, btr = 0, bti = 0, bpr = 0, bpi = 0, ctr = 0, cti = 0, cpr = 0, cpi = 0;
-      for (int j = 0; j < nl; ++j) {
-        const R w = wl[j];
-        const R pw = w * Lp[j], dw = w * Ld[j], qw = w * Lq[j];
-        const R* Fr = F + ((0 * nl + j) * M1 + m) * 2;
-        const R* Ft = F + ((1 * nl + j) * M1 + m) * 2;
-        const R* Fp = F + ((2 * nl + j) * M1 + m) * 2;
-        ar += pw * Fr[0];
-        ai += pw * Fr[1];
-        btr += dw * Ft[0];
-        bti += dw * Ft[1];
-        bpr += dw * Fp[0];
-        bpi += dw * Fp[1];
-        ctr += qw * Ft[0];
-        cti += qw * Ft[1];
-        cpr += qw * Fp[0];
-        cpi += qw * Fp[1];
+      R gr, gi, xnr, xni, ar, ai;
+      if (MF) {
+        gr = PJ[6 * i];
+        gi = PJ[6 * i + 1];
+        xnr = PJ[6 * i + 2];
+        xni = PJ[6 * i + 3];
+        ar = PJ[6 * i + 4];
+        ai = PJ[6 * i + 5];
+      } else {
+        const R* Lp = leg + ((size_t)0 * nc + i) * nl;
+        const R* Ld = leg + ((size_t)1 * nc + i) * nl;
+        const R* Lq = leg + ((size_t)2 * nc + i) * nl;
+        R sar = 0, sai = 0, btr = 0, bti = 0, bpr = 0, bpi = 0, ctr = 0, cti = 0, cpr = 0, cpi = 0;
+        for (int j = 0; j < nl; ++j) {
+          const R w = wl[j];
+          const R pw = w * Lp[j], dw = w * Ld[j], qw = w * Lq[j];
+          const R* Fr = F + ((0 * nl + j) * M1 + m) * 2;
+          const R* Ft = F + ((1 * nl + j) * M1 + m) * 2;
+          const R* Fp = F + ((2 * nl + j) * M1 + m) * 2;
+          sar += pw * Fr[0];
+          sai += pw * Fr[1];
+          btr += dw * Ft[0];
+          bti += dw * Ft[1];
+          bpr += dw * Fp[0];
+          bpi += dw * Fp[1];
+          ctr += qw * Ft[0];
+          cti += qw * Ft[1];
+          cpr += qw * Fp[0];
+          cpi += qw * Fp[1];
+        }
+        gr = btr + cpi;
+        gi = bti - cpr;
+        xnr = bpr - cti;
+        xni = bpi + ctr;
+        ar = sar;
+        ai = sai;
       }
-      // V = (b_t - i c_p - (n+1) a) / ((n+1)(2n+1)); W = (b_t - i c_p + n a) / (n(2n+1));
-      // X = (b_p + i c_t) / (n(n+1))
-      const R gr = btr + cpi, gi = bti - cpr;
       const R nn = (R)n;
       R vr = (gr - (nn + 1) * ar) / ((nn + 1) * (2 * nn + 1));
       R vi = (gi - (nn + 1) * ai) / ((nn + 1) * (2 * nn + 1));
@@ -164,8 +255,8 @@ __global__ __launch_bounds__(256) void vsh_kernel(VshParams a) {
       if (n >= 1) {
         wr = (gr + nn * ar) / (nn * (2 * nn + 1));
         wi = (gi + nn * ai) / (nn * (2 * nn + 1));
-        xr = (bpr - cti) / (nn * (nn + 1));
-        xi = (bpi + ctr) / (nn * (nn + 1));
+        xr = xnr / (nn * (nn + 1));
+        xi = xni / (nn * (nn + 1));
       }
       if (a.coef_out) {
         double* co = a.coef_out + (size_t)k * 3 * nc * 2;
@@ -250,7 +341,50 @@ __global__ __launch_bounds__(256) void vsh_kernel(VshParams a) {
 
   // ---- Legendre synthesis per latitude (Eqs. 2.9-2.10 written with dPbar, m Pbar/s) --
   //   F_r = sum_n Pbar Y;  F_t = sum_n (dPbar G - i mQ X);  F_p = sum_n (i mQ G + dPbar X)
-  for (int e = tid; e < nl * M1; e += nt) {
+  if (MF) {
+    // tile rows j = 16 jt + (0..15), K = degrees n, columns
+    //   0: Re F_t  1: Im F_t  2: Re F_p  3: Im F_p  4: Re F_r  5: Im F_r
+    // from dPbar x [Re G, Im G, Re X, Im X] + mQ x [Im X, -Re X, -Im G, Re G] +
+    // Pbar x [0, 0, 0, 0, Re Y, Im Y]
+    const int col = lane & 15, kq = lane >> 4;
+    for (int task = wv; task < 2 * M1; task += nw) {
+      const int m = task >> 1, jt = task & 1;
+      if (16 * jt >= nl) continue;   // wave-uniform
+      const int off = m * (a.p + 1) - (m * (m - 1)) / 2;
+      const int L = a.p + 1 - m;
+      const int jA = 16 * jt + col;
+      const bool jok = jA < nl;
+      const int jc = jok ? jA : 0;
+      typename Tile<R>::T acc = {0, 0, 0, 0};
+      for (int ks = 0; ks < (L + 3) / 4; ++ks) {
+        const int dn = 4 * ks + kq;
+        const bool nok = dn < L;
+        const int i = off + (nok ? dn : 0);
+        const R am = (jok && nok) ? (R)1 : (R)0;
+        const R ap = am * leg[((size_t)0 * nc + i) * nl + jc];
+        const R ad = am * leg[((size_t)1 * nc + i) * nl + jc];
+        const R aq = am * leg[((size_t)2 * nc + i) * nl + jc];
+        const R bm = nok ? (R)1 : (R)0;
+        const R yr = bm * C[(0 * nc + i) * 2], yi = bm * C[(0 * nc + i) * 2 + 1];
+        const R gr = bm * C[(1 * nc + i) * 2], gi = bm * C[(1 * nc + i) * 2 + 1];
+        const R xr = bm * C[(2 * nc + i) * 2], xi = bm * C[(2 * nc + i) * 2 + 1];
+        const R bd = col == 0 ? gr : col == 1 ? gi : col == 2 ? xr : col == 3 ? xi : (R)0;
+        const R bq = col == 0 ? xi : col == 1 ? -xr : col == 2 ? -gi : col == 3 ? gr : (R)0;
+        const R bp = col == 4 ? yr : col == 5 ? yi : (R)0;
+        acc = Tile<R>::step(ad, bd, acc);
+        acc = Tile<R>::step(aq, bq, acc);
+        acc = Tile<R>::step(ap, bp, acc);
+      }
+      if (col < 6) {
+        const int c = col < 2 ? 1 : col < 4 ? 2 : 0;
+        for (int v = 0; v < 4; ++v) {
+          const int j = 16 * jt + Tile<R>::row(kq, v);
+          if (j < nl) F[((c * nl + j) * M1 + m) * 2 + (col & 1)] = acc[v];
+        }
+      }
+    }
+  }
+  for (int e = MF ? nl * M1 : tid; e < nl * M1; e += nt) {
     const int j = e / M1, m = e - j * M1;
     const int off = m * (a.p + 1) - (m * (m - 1)) / 2;
     R rr = 0, ri = 0, tr = 0, ti = 0, pr = 0, pi = 0;
@@ -358,7 +492,7 @@ __global__ __launch_bounds__(256) void vsh_kernel(VshParams a) {
 }
 
 static size_t vsh_smem(const bie_ctx* c, size_t rs) {
-  size_t b = rs * (3 * (size_t)c->P + 3 * (size_t)c->nlat * (c->mmax + 1) * 2 + 3 * (size_t)c->ncoef * 2);
+  size_t b = rs * (3 * (size_t)c->P + 3 * (size_t)c->nlat * (c->mmax + 1) * 2 + 12 * (size_t)c->ncoef);
   b = (b + 15) & ~size_t(15);
   return b + 64 * sizeof(double);
 }
@@ -405,10 +539,15 @@ void launch_vsh(bie_ctx* c, int precision, const VshCall& v) {
   for (int f = 0; f < 3; ++f)
     for (int n = 0; n < 33; ++n) a.lamS[f][n] = v.lamS[f][n];
   const size_t sm = vsh_smem(c, f32 ? sizeof(float) : sizeof(double));
-  if (f32)
-    vsh_kernel<float><<<dim3((unsigned)c->nb), dim3(256), sm, c->stream>>>(a);
+  const dim3 grid((unsigned)c->nb), block(256);
+  if (f32 && c->legendre_mfma)
+    vsh_kernel<float, true><<<grid, block, sm, c->stream>>>(a);
+  else if (f32)
+    vsh_kernel<float, false><<<grid, block, sm, c->stream>>>(a);
+  else if (c->legendre_mfma)
+    vsh_kernel<double, true><<<grid, block, sm, c->stream>>>(a);
   else
-    vsh_kernel<double><<<dim3((unsigned)c->nb), dim3(256), sm, c->stream>>>(a);
+    vsh_kernel<double, false><<<grid, block, sm, c->stream>>>(a);
   BIE_HIP(hipGetLastError());
 }
 
