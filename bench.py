@@ -118,7 +118,8 @@ def main():
                     help="only run a 1 GiB device-to-device copy (HBM byte-counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (the far field would shard "
+              "by target spheres with one all-gather of the source strengths per matvec)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -2,8 +2,9 @@
 
 Test infrastructure only (see ``oracle/__init__.py``).
 
-The paper gives no preconditioner; this is the learned block correction of the
-spec design, written here from its definition:
+The paper gives no preconditioner; this is a learned block correction (an addition to
+the method: a small per-sphere network over neighbour geometry that predicts the
+coupling of close pairs), written here from its definition:
 
     M_MLP r = M0 r + P zeta,   zeta_i = sum_{j in near(i)} Q_ij^T [K_off(theta_ij) Q_ij rho_j
                                                               + K_self(theta_ij) Q_ij rho_i],
