@@ -9,8 +9,9 @@ the timed region.  value = far-field pair interactions evaluated / wall time.
 
 Reported beside it: the time-to-solution of plain float64 GMRES (no preconditioner) on
 the same GPU, the roofline of the dominant kernel (float32 far-field pair sum, timed
-live with HIP events on the library's stream), and the CPU oracle's pair rate on a
-bounded sample of the same workload.
+live with HIP events on the library's stream), the time-to-solution as a fraction of its
+own roofline (every matvec's far-field flop at the vector peak of its precision), and
+the CPU oracle's pair rate on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -208,10 +209,21 @@ def main():
                      "launch_ms": t_far64 * 1e3, "pairs_per_s": pairs_per_mv / t_far64},
         "far_fp32_pairs_per_s": pairs_per_mv / t_far32,
     }
+    # time-to-solution against its roofline: the far-field flop of every matvec of the
+    # solve at the vector peak of the precision it runs in
+    flop_mv = pairs_per_mv * FLOP_PER_PAIR[kind]
+    ideal = (infos[-1]["matvecs_mixed"] * flop_mv / (PEAK_FP32_VECTOR_TFLOPS * 1e12)
+             + infos[-1]["matvecs_fp64"] * flop_mv / (PEAK_FP64_VECTOR_TFLOPS * 1e12))
+    out["time_to_solution_roofline"] = {
+        "ideal_s": ideal, "frac": ideal / tts,
+        "model": f"far-field flop ({FLOP_PER_PAIR[kind]} per pair) of each matvec at the float32 "
+                 f"({PEAK_FP32_VECTOR_TFLOPS}) or float64 ({PEAK_FP64_VECTOR_TFLOPS} TFLOP/s) vector peak"}
     if ref is not None:
         out["time_to_solution_fp64_plain_s"] = ref["seconds"]
         out["fp64_plain_iters"] = ref["iters"]
         out["speedup_vs_fp64_plain"] = ref["seconds"] / tts
+        ideal64 = ref["matvecs_fp64"] * flop_mv / (PEAK_FP64_VECTOR_TFLOPS * 1e12)
+        out["time_to_solution_fp64_plain_roofline_frac"] = ideal64 / ref["seconds"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
     sph.close()
