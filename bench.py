@@ -33,14 +33,26 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 
 
+def code_sha(path):
+    """First 16 hex digits of the SHA-256 of a C++ / HIP source with its // comments,
+    trailing blanks and empty lines removed: changes to the code change it, comment
+    edits do not.  (No string literal in the kernel sources holds //.)"""
+    import hashlib
+    lines = []
+    for line in open(path, encoding="utf-8").read().splitlines():
+        code = line.split("//", 1)[0].rstrip()
+        if code:
+            lines.append(code)
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()[:16]
+
+
 def measured_traffic():
     """HBM bytes per launch of the far-field kernel from the committed PMC summary, or
-    None when the kernel source has changed since the counters were taken."""
-    import hashlib
+    None when the kernel's code has changed since the counters were taken."""
     src = os.path.join(ROOT, "paper_1707_06551_amd", "csrc", "p2p.hip")
     prof = os.path.join(ROOT, "profiles", "far_kernel_spheres512_p12_pmc.md")
     try:
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        sha = code_sha(src)
         fields = dict(l.split(": ", 1) for l in open(prof).read().splitlines() if ": " in l and l[:1].isalpha())
         if fields.get("source_sha256_16", "").strip() == sha:
             return float(fields["traffic_bytes_per_launch"])

@@ -22,7 +22,7 @@
 // 1 + 6 (r.n)/r^2 is rewritten with r.n = (|p|^2 - 1 - r.r)/2 as
 // 3 (|p|^2 - 1)/r^2 - 2, one fused multiply-add per pair with 3 (|p|^2 - 1) formed once
 // per (target, source sphere); the factor stays near 1 (|p| <= r + 1), so this costs no
-// cancellation.  Per pair: S+D 18 VALU + 1 rsqrt, D 17, S 16, K 17.  All inner-loop operands
+// cancellation.  Per pair: S+D 18 VALU + 1 rsqrt, D 17, S 16, K 18.  All inner-loop operands
 // are VGPRs, literals or inline constants: on gfx950 a float32 VALU instruction with an
 // SGPR operand issues at half the rate of one without (measured), which is why float32
 // sources are staged in LDS rather than read through the scalar cache.  Self and near source spheres are skipped through a per-target bit mask (a whole
