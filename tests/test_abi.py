@@ -44,3 +44,33 @@ def test_null_arguments_are_rejected_without_a_device():
     L.bie_build_spheres.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
     L.bie_build_spheres.restype = ctypes.c_int
     assert L.bie_build_spheres(None, 0, None, None) == -1
+
+
+def test_options_struct_matches_the_header():
+    # field order and types of bie_opts in include/bie.h against the binding's mirror
+    from paper_1707_06551_amd import bie
+    body = re.search(r"typedef struct \{(.*?)\} bie_opts;", open(HEADER).read(), re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"\b(int|double|void\*)\s+(\w+);", body)
+    ctype = {"int": ctypes.c_int, "double": ctypes.c_double, "void*": ctypes.c_void_p}
+    assert [(n, ctype[t]) for t, n in fields] == list(bie.Opts._fields_)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libbie.so not built")
+@pytest.mark.parametrize("bad", [dict(p=0), dict(p=21), dict(n_phi=7), dict(n_phi=6), dict(near_method=2),
+                                 dict(legendre_mfma=2), dict(n_spheres=0), dict(n_spheres=65537)])
+def test_invalid_options_are_rejected_before_any_device_call(bad):
+    import numpy as np
+    from paper_1707_06551_amd import bie
+    L = ctypes.CDLL(LIB)
+    L.bie_build_spheres.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
+    L.bie_build_spheres.restype = ctypes.c_int
+    L.bie_last_error.restype = ctypes.c_char_p
+    kw = dict(p=4, n_phi=0, near_method=0, legendre_mfma=0, n_spheres=2)
+    kw.update(bad)
+    o = bie.Opts(kw["p"], kw["n_phi"], 1.0, 0, None, kw["near_method"], kw["legendre_mfma"])
+    centres = np.arange(3 * max(kw["n_spheres"], 1), dtype=np.float64) * 3.0
+    h = ctypes.c_void_p()
+    rc = L.bie_build_spheres(centres.ctypes.data, kw["n_spheres"], ctypes.byref(o), ctypes.byref(h))
+    assert rc == -1 and h.value is None, (rc, L.bie_last_error())
+    assert L.bie_last_error()
