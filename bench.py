@@ -67,22 +67,25 @@ def far_pairs(sph):
     return (sph.nb * (sph.nb - 1) - near) * sph.P * sph.P
 
 
-def time_far_stage(sph, torch, bie, precision, reps=10):
-    """Average duration of one far-field pass (S+D), timed with events on the stream the
-    library launches on (torch's current stream, passed at context creation)."""
+def time_far_stage(sph, torch, bie, precision, reps=20, warmup=3):
+    """Median and mean duration (s) of one far-field pass (S+D: the pair-sum kernel and
+    the reduction of its split partial sums), each pass bracketed by its own events on
+    the stream the library launches on (torch's current stream, passed at context
+    creation); `warmup` untimed passes first."""
     x = torch.randn(3 * sph.N, dtype=torch.float64, device="cuda")
     u = torch.empty_like(x)
     op = bie.OP_SD_BIE | bie.STAGE_FAR
-    sph.apply(op, x, u, precision=precision)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
+    for _ in range(warmup):
         sph.apply(op, x, u, precision=precision)
-    e1.record()
-    e1.synchronize()
-    return e0.elapsed_time(e1) / reps / 1e3
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record()
+        sph.apply(op, x, u, precision=precision)
+        e1.record()
+    torch.cuda.synchronize()
+    ms = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+    return float(np.median(ms)) / 1e3, float(ms.mean()) / 1e3
 
 
 def cpu_baseline(w, seconds_target=15.0):
@@ -181,8 +184,8 @@ def main():
     if not args.no_fp64:
         ref = solve(bie.FP64, bie.PC_NONE)[-1]
 
-    t_far32 = time_far_stage(sph, torch, bie, bie.MIXED)
-    t_far64 = time_far_stage(sph, torch, bie, bie.FP64)
+    t_far32, t_far32_mean = time_far_stage(sph, torch, bie, bie.MIXED)
+    t_far64, t_far64_mean = time_far_stage(sph, torch, bie, bie.FP64)
     kind = "SD" if mobility else "D"
     ach32 = pairs_per_mv * FLOP_PER_PAIR[kind] / t_far32 / 1e12
     ach64 = pairs_per_mv * FLOP_PER_PAIR[kind] / t_far64 / 1e12
@@ -216,9 +219,12 @@ def main():
                      "frac": ach32 / PEAK_FP32_VECTOR_TFLOPS, "traffic": measured_traffic(),
                      "traffic_unit": "bytes per launch (HBM, PMC FETCH_SIZE + WRITE_SIZE, calibrated)",
                      "flop_per_pair": FLOP_PER_PAIR[kind], "launch_ms": t_far32 * 1e3,
+                     "launch_ms_mean": t_far32_mean * 1e3,
+                     "timing": "median of 20 event-timed far-field passes after 3 warm-up passes",
                      "pairs_per_launch": pairs_per_mv},
         "far_fp64": {"achieved_tflops": ach64, "peak": PEAK_FP64_VECTOR_TFLOPS, "frac": ach64 / PEAK_FP64_VECTOR_TFLOPS,
-                     "launch_ms": t_far64 * 1e3, "pairs_per_s": pairs_per_mv / t_far64},
+                     "launch_ms": t_far64 * 1e3, "launch_ms_mean": t_far64_mean * 1e3,
+                     "pairs_per_s": pairs_per_mv / t_far64},
         "far_fp32_pairs_per_s": pairs_per_mv / t_far32,
     }
     # time-to-solution against its roofline: the far-field flop of every matvec of the
