@@ -24,10 +24,19 @@ target sphere (degree <= p, |m| <= mmax), not its pointwise values; the direct m
 (operators.near_part) evaluates the series at the nodes themselves.  D^n is computed
 here by its definition, a quadrature projection exact for degree n.
 
+Spheres of radii a_s (source) and a_t (target): the steps run in units of the source
+radius, where the source is a unit sphere again: the target grid sits at
+(0, 0, |d| / a_s) + (a_t / a_s) x_jl (each latitude still at fixed (r, theta)), and the
+single layer's series carries the factor a_s (its kernel is homogeneous of degree -1 in
+length, the area element of degree 2; the double layer is scale-free).  The angular
+steps (rotations, projection on the target grid) do not see the radii.
+
 Parity: pinned by tests/test_oracle_rotation.py (D^n is unitary, D^n(R_z(a)) is the
 phase e^{-i m a}, rotated coefficients resynthesise the rotated field; a pair already on
-the pole reduces to the projection of the direct series; for smooth densities the
-result converges to the direct series as p grows).
+the pole reduces to the projection of the direct series, also for spheres of two radii;
+for smooth densities the result converges to the direct series as p grows, also with
+radii; scaling a configuration by lam scales the single layer's result by lam and
+leaves the double layer's unchanged).
 """
 import math
 
@@ -114,15 +123,16 @@ def series_at(coef_full, p, x, a_s, a_d):
     return out.real
 
 
-def pair_coefficients(geom, coef_s, d, a_s, a_d, vsh=None):
+def pair_coefficients(geom, coef_s, d, a_s, a_d, vsh=None, rad_s=1.0, rad_t=1.0):
     """Stages 1-3 for one directed pair: the target's coefficients (mode_list(p, mmax))
-    of the near field of the source density with coefficients coef_s (3, M)."""
+    of the near field of the source density with coefficients coef_s (3, M); rad_s and
+    rad_t the radii of the source and target spheres."""
     p, mmax = geom.p, geom.mmax
     vsh = vsh or DenseVSH(geom.grid, p, mmax)
     Q = rotation_to_pole(d)
     cR = rotate(expand(coef_s, p, mmax), p, Q)
-    x = np.array([0.0, 0.0, np.linalg.norm(d)])[None, :] + geom.grid["xhat"]
-    uR = series_at(cR, p, x, a_s, a_d)
+    x = np.array([0.0, 0.0, np.linalg.norm(d) / rad_s])[None, :] + (rad_t / rad_s) * geom.grid["xhat"]
+    uR = series_at(cR, p, x, a_s * rad_s, a_d)
     uhatR = vsh.forward(uR)
     return truncate(rotate(expand(uhatR, p, mmax), p, Q.T), p, mmax)
 
@@ -142,6 +152,6 @@ def near_part(geom, mu, a_s, a_d):
         for s in srcs:
             if s not in coefs:
                 coefs[s] = vsh.forward(mu[g.sphere_nodes(s)])
-            acc += pair_coefficients(g, coefs[s], g.centres[t] - g.centres[s], a_s, a_d, vsh)
+            acc += pair_coefficients(g, coefs[s], g.centres[t] - g.centres[s], a_s, a_d, vsh, g.radii[s], g.radii[t])
         out[g.sphere_nodes(t)] = vsh.inverse(acc)
     return out
