@@ -22,6 +22,12 @@
 // The result is the band-limited projection of the near field on the target sphere, not
 // its values at the nodes.  One work-group per target sphere, float64, vectors and
 // per-pair Fourier coefficients in LDS, deterministic order, no atomics.
+// Spheres of radii a_s (source) and a_t (target): steps 1-3 run in units of a_s, where
+// the source is a unit sphere: the translated grid sits at (0, 0, L / a_s) + (a_t / a_s) x
+// (still a fixed (r, theta) per latitude) and the single layer's radial constants carry
+// the factor a_s; rotations and the projection are angular and do not see the radii.
+// The constants of the current pair are formed in LDS (for unit spheres they are the
+// operator's own: a_s = 1 and no separate single-layer part).
 #include "bie_internal.h"
 #include "series.h"
 
@@ -41,8 +47,16 @@ struct RotParams {
   const double* tlat;      // nlat cos(theta_j)
   const double* wig;       // per n, (2n+1)^2 complex (re, im): row m' + n, column m + n holds E_n[m', m]
   double* out;             // nb x 3 x ncoef x 2 accumulated target coefficients
+  const double* radius;    // nb radii, or NULL for unit spheres
   int p, mmax, ncoef, nlat, nphi;
-  double kvv[33], kww[33], kwv[33], kxx[33];
+  double kvv[33], kww[33], kwv[33], kxx[33];   // a_S S + a_D D (unit) or a_D D (radii)
+  double sv[33], sw[33], swv[33], sx[33];      // a_S S (radii; zero for unit spheres)
+};
+
+// radial constants of the current pair (LDS), read by series_order
+struct RotK {
+  int p, mmax, ncoef;
+  const double *kvv, *kww, *kwv, *kxx;
 };
 
 __device__ inline int wig_off(int n) { return n * (2 * n - 1) * (2 * n + 1) / 3; }
@@ -82,6 +96,8 @@ __global__ __launch_bounds__(256) void near_rot_kernel(RotParams a) {
   double* sa = ca + (p + 1);
   double* cb = sa + (p + 1);
   double* sb = cb + (p + 1);
+  double* kc = sb + (p + 1);           // 4 x 33 radial constants of the current pair
+  const RotK kr{p, mmax, nc, kc, kc + 33, kc + 66, kc + 99};
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int i = tid; i < 6 * nc; i += nt) {
     rec[i] = a.rec[i];
@@ -89,6 +105,7 @@ __global__ __launch_bounds__(256) void near_rot_kernel(RotParams a) {
   }
   const int s0 = a.near_ptr[t], s1 = a.near_ptr[t + 1];
   const double ctx = a.centres4[4 * t], cty = a.centres4[4 * t + 1], ctz = a.centres4[4 * t + 2];
+  const double rt = a.radius ? a.radius[t] : 1.0;
   const auto Ucoef = [U, nc](int f, int i) { return U + 2 * (f * nc + i); };
   for (int e = s0; e < s1; ++e) {
     const int s = a.near_idx[e];
@@ -97,10 +114,16 @@ __global__ __launch_bounds__(256) void near_rot_kernel(RotParams a) {
     const double al = atan2(dy, dx);
     const double be = acos(fmin(1.0, fmax(-1.0, dz / L)));
     const double* cs = a.coef + (size_t)s * 6 * nc;
+    const double rs = a.radius ? a.radius[s] : 1.0;
+    const double Ls = L / rs, rho = rt / rs;   // in units of the source radius
     __syncthreads();
     for (int m = tid; m <= p; m += nt) {
       sincos(m * al, &sa[m], &ca[m]);
       sincos(m * be, &sb[m], &cb[m]);
+      kc[m] = fma(rs, a.sv[m], a.kvv[m]);
+      kc[33 + m] = fma(rs, a.sw[m], a.kww[m]);
+      kc[66 + m] = fma(rs, a.swv[m], a.kwv[m]);
+      kc[99 + m] = fma(rs, a.sx[m], a.kxx[m]);
     }
     __syncthreads();
     // 1a. A = diag(e^{i m a}) c
@@ -154,10 +177,10 @@ __global__ __launch_bounds__(256) void near_rot_kernel(RotParams a) {
     for (int it = tid; it < nl * M1; it += nt) {
       const int j = it / M1, m = it - j * M1;
       const double tj = a.tlat[j], sj = sqrt(fmax(0.0, 1.0 - tj * tj));
-      const double z = L + tj;
-      const double r = sqrt(sj * sj + z * z);
+      const double z = Ls + rho * tj, h = rho * sj;
+      const double r = sqrt(h * h + z * z);
       const double ir = 1.0 / r, ir2 = ir * ir;
-      const double ct = z * ir, st = sj * ir;
+      const double ct = z * ir, st = h * ir;
       double pmm = 0.28209479177387814, qmm = 0.0, irm = 1.0;
       for (int q = 1; q <= m; ++q) {
         const double fq = rec[6 * (q * (p + 1) - (q * (q - 1)) / 2) + 5];
@@ -166,7 +189,7 @@ __global__ __launch_bounds__(256) void near_rot_kernel(RotParams a) {
         irm *= ir;
       }
       double sv[6];
-      series_order(a, Ucoef, rec, m, ct, st, ir, ir2, irm, pmm, qmm, sv);
+      series_order(kr, Ucoef, rec, m, ct, st, ir, ir2, irm, pmm, qmm, sv);
       const double cd = ct * tj + st * sj, sd = st * tj - ct * sj;   // cos, sin (theta_s - theta_j)
       const double g = (double)a.nphi;
       double* Fr = F + 2 * ((0 * nl + j) * M1 + m);
@@ -274,7 +297,8 @@ __global__ __launch_bounds__(256) void near_rot_kernel(RotParams a) {
 
 static size_t rot_smem(const bie_ctx* c) {
   const size_t nfull = (size_t)(c->p + 1) * (c->p + 1);
-  return sizeof(double) * (12 * nfull + 18 * (size_t)c->ncoef + 6 * (size_t)c->nlat * (c->mmax + 1) + 4 * (c->p + 1));
+  return sizeof(double) *
+         (12 * nfull + 18 * (size_t)c->ncoef + 6 * (size_t)c->nlat * (c->mmax + 1) + 4 * (c->p + 1) + 4 * 33);
 }
 
 void launch_near_rot(bie_ctx* c, const OpSpec& spec, double* u) {
@@ -296,7 +320,13 @@ void launch_near_rot(bie_ctx* c, const OpSpec& spec, double* u) {
   a.ncoef = c->ncoef;
   a.nlat = c->nlat;
   a.nphi = c->n_phi;
-  series_radial(spec.a_s, spec.a_d, c->p, a.kvv, a.kww, a.kwv, a.kxx);
+  if (c->poly) {
+    a.radius = c->radius_d.as<double>();
+    series_radial(0.0, spec.a_d, c->p, a.kvv, a.kww, a.kwv, a.kxx);
+    series_radial(spec.a_s, 0.0, c->p, a.sv, a.sw, a.swv, a.sx);
+  } else {
+    series_radial(spec.a_s, spec.a_d, c->p, a.kvv, a.kww, a.kwv, a.kxx);   // a.sv... stay zero
+  }
   const size_t sm = rot_smem(c);
   BIE_HIP(hipFuncSetAttribute((const void*)near_rot_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm));
   near_rot_kernel<<<dim3((unsigned)c->nb), dim3(256), sm, c->stream>>>(a);

@@ -271,8 +271,6 @@ void build(bie_ctx* c, const double* centres, const double* radii, int64_t nb, c
     if (a != 1.0) c->poly = true;
   }
   const double* rad = c->radius.data();
-  if (c->poly && c->near_method != 0)
-    throw Error{BIE_EINVAL, "near_method 1 (pole rotation) is built for unit spheres only"};
 
   // ---- near pairs (Eq. 4.5 as a surface-gap test) with a uniform cell list --------
   // unit spheres: near when |c_t - c_s| - 2 < d*; radii a: when the gap

@@ -342,6 +342,10 @@ def test_polydisperse_rejects_unit_only_features(cluster):
     with pytest.raises(bie.BieError):
         s.apply_precond(bie.OP_SD_BIE, mu, precond=bie.PC_MLP)
     with pytest.raises(bie.BieError):
-        bie.Spheres(c, 4, radii=a, near_method=1)
-    with pytest.raises(bie.BieError):
         bie.Spheres(c, 4, radii=np.full(len(a), 1.2))   # overlapping
+    with pytest.raises(bie.BieError):
+        s_rot = bie.Spheres(c, 4, radii=a, near_method=1)
+        try:
+            s_rot.apply(bie.OP_K, mu[:3 * s_rot.N])       # the traction has no rotation variant
+        finally:
+            s_rot.close()
