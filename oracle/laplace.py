@@ -1,4 +1,4 @@
-"""Laplace layer potentials on unit spheres (Section 3.1, Theorem 1) and the magnetostatic
+"""Laplace layer potentials on spheres (Section 3.1, Theorem 1) and the magnetostatic
 problem of Problem 3 (Eqs. 5.9-5.13): the definitions the HIP path must reproduce.
 
 Test infrastructure only (see ``oracle/__init__.py``).
@@ -21,6 +21,12 @@ Test infrastructure only (see ``oracle/__init__.py``).
   force and torque on sphere k are int t and int (x - c_k) x t (Eq. 4.4 quadrature).
   The fluid couples to the field only through these (Section 5), which the mobility
   problem then takes as applied loads.
+* Spheres of radius a (geometry with radii: nodes c + a x, weights a^2 w): S^L of a
+  sphere of radius a is a times the unit-sphere layer at (x - c)/a (kernel of degree -1
+  in length, area element of degree 2), so the own-sphere value carries a, the series
+  is evaluated at (x - c)/a with its value times a, and the gradient and K^L are
+  scale-free; the quadrature uses the actual nodes and weights; the torque arm is
+  x - c = a n.
 
 Parity: pinned by tests/test_oracle_laplace.py (Theorem 1 by brute-force quadrature;
 the textbook magnetisable sphere in a uniform field; the gradient against finite
@@ -64,10 +70,11 @@ class Laplace:
         return (c @ self.Y).real
 
     # ---- values / gradients at arbitrary exterior points of one source sphere -------
-    def series(self, c, centre, x):
-        """S^L of the density with coefficients c on the sphere at centre: value (K,) and
-        gradient (K, 3) at points x (K, 3) outside it (Eq. 3.3)."""
-        d = x - centre[None, :]
+    def series(self, c, centre, x, radius=1.0):
+        """S^L of the density with coefficients c on the sphere of the given radius at
+        centre: value (K,) and gradient (K, 3) at points x (K, 3) outside it (Eq. 3.3,
+        in units of the radius)."""
+        d = (x - centre[None, :]) / radius
         r = np.linalg.norm(d, axis=1)
         modes, Y, Dt, Dp, er, eth, eph = ylm_at(d / r[:, None], self.g.p, self.g.mmax)
         n = np.array([nn for (nn, _m) in modes])[:, None]
@@ -78,12 +85,13 @@ class Laplace:
         gt = (c[:, None] * (f / r[None, :]) * Dt).sum(0).real
         gp = (c[:, None] * (f / r[None, :]) * Dp).sum(0).real
         grad = gr[:, None] * er + gt[:, None] * eth + gp[:, None] * eph
-        return val, grad
+        return radius * val, grad
 
-    def direct(self, q_sphere, centre, x):
-        """Smooth quadrature of S^L and its gradient from one sphere's nodes."""
-        y = centre[None, :] + self.g.grid["xhat"]
-        qw = q_sphere * self.g.grid["wnode"]
+    def direct(self, q_sphere, centre, x, radius=1.0):
+        """Smooth quadrature of S^L and its gradient from one sphere's nodes (Eq. 4.4 on
+        the sphere of the given radius: nodes c + a x, weights a^2 w)."""
+        y = centre[None, :] + radius * self.g.grid["xhat"]
+        qw = q_sphere * radius ** 2 * self.g.grid["wnode"]
         r = x[:, None, :] - y[None, :, :]
         d = np.linalg.norm(r, axis=2)
         val = (qw[None, :] / d).sum(1) / (4 * math.pi)
@@ -104,7 +112,7 @@ class Laplace:
         for t in range(g.nb):
             sl = g.sphere_nodes(t)
             c = coefs[t] if self_term else 0.0 * coefs[t]
-            val[sl] = self.synth(c / (2 * n + 1))
+            val[sl] = g.radii[t] * self.synth(c / (2 * n + 1))
             # sum c / (2n+1) (grad_s Y - (n+1) Y e_r)
             a = c[:, None] / (2 * n + 1)[:, None]
             gt = (a * self.Dt).sum(0).real
@@ -116,9 +124,9 @@ class Laplace:
                 if s == t:
                     continue
                 if g.near[t, s]:
-                    v, gd = self.series(coefs[s], g.centres[s], x)
+                    v, gd = self.series(coefs[s], g.centres[s], x, g.radii[s])
                 else:
-                    v, gd = self.direct(q[g.sphere_nodes(s)], g.centres[s], x)
+                    v, gd = self.direct(q[g.sphere_nodes(s)], g.centres[s], x, g.radii[s])
                 val[sl] += v
                 grad[sl] += gd
         return val, grad
@@ -160,5 +168,6 @@ def solve_magnetic(geom, H0, eta):
     t = Hn[:, None] * H - 0.5 * np.einsum("gi,gi->g", H, H)[:, None] * nrm
     wt = geom.w[:, None] * t
     F = wt.reshape(geom.nb, geom.P, 3).sum(1)
-    T = np.cross(nrm, wt).reshape(geom.nb, geom.P, 3).sum(1)
+    arm = geom.nodes - np.repeat(geom.centres, geom.P, axis=0)     # x - c = a n
+    T = np.cross(arm, wt).reshape(geom.nb, geom.P, 3).sum(1)
     return q, F, T, H
