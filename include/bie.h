@@ -119,9 +119,10 @@ int bie_build_spheres(const double* centres, int64_t n_spheres, const bie_opts* 
  * sphere), with BIE_PC_NONE or BIE_PC_M0 (per-sphere isolated inverses), the resistance
  * form also with BIE_PC_M0 | BIE_PC_RIGID (the coarse operator of spheres of radius a,
  * see BIE_PC_RIGID), bie_eval_field (near test |x - c_k| - a_k < near_gap a_k), the
- * transforms, nodes and near pairs, and near_method 1 (the pole rotation in units of
- * the source radius); the learned correction and the Laplace / magnetic problem return
- * BIE_EINVAL. */
+ * transforms, nodes and near pairs, near_method 1 (the pole rotation in units of the
+ * source radius), and bie_apply_laplace / bie_solve_magnetic (S^L of a sphere of
+ * radius a is a times the unit layer at (x - c)/a: gradient and K^L scale-free; force
+ * and torque carry a^2 and a^3); the learned correction returns BIE_EINVAL. */
 int bie_build_spheres_radii(const double* centres, const double* radii, int64_t n_spheres, const bie_opts* opts,
                             bie_ctx** out);
 

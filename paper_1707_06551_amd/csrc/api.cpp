@@ -564,7 +564,7 @@ int bie_apply_laplace(bie_ctx* c, int kind, double eta, const double* q, double*
     bie::set_error("bie_apply_laplace: bad arguments");
     return BIE_EINVAL;
   }
-  BIE_TRY(bie::require_unit(c, "bie_apply_laplace"); if (kind == 0) {
+  BIE_TRY(if (kind == 0) {
     c->lap_eta = eta;
     bie::lap_apply(c, q, out);
   } else {
@@ -581,7 +581,6 @@ int bie_solve_magnetic(bie_ctx* c, const double* H0, double eta, const bie_solve
   }
   int rc = BIE_OK;
   BIE_TRY({
-    bie::require_unit(c, "bie_solve_magnetic");
     bie::DevBuf qtmp;
     double* qd = q;
     if (!qd) {

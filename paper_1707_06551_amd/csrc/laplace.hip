@@ -12,6 +12,13 @@
 // the library's GMRES; H = H0 - grad S^L[q] on the fluid side; the Maxwell traction
 // t = (H . n) H - |H|^2 n / 2 (mu0 = 1) gives each sphere's force int t and torque
 // int (x - c) x t, the loads through which the field moves the particles.
+//
+// Spheres of radius a: S^L of a sphere of radius a is a times the unit-sphere layer at
+// (x - c)/a, so its gradient and K^L are scale-free.  The own-sphere terms (K_pv, the
+// gradient, the block inverse) are unchanged; near and far sources are evaluated at the
+// target node written in units of the source radius, (c_t + a_t o - c_s)/a_s, with the
+// unit-sphere series and quadrature; force and torque carry a^2 (area) and a^3 (area
+// and lever arm).
 #include <algorithm>
 
 #include "bie_internal.h"
@@ -148,6 +155,7 @@ struct NearLapParams {
   const int* near_idx;
   const double* otab;      // P x 4
   const double* rec;       // ncoef x 6
+  const double* radius;    // nb radii, or nullptr for unit spheres
   double* out;             // N: += scale * n . grad  (or nullptr)
   double* grad;            // N x 3: += grad          (or nullptr)
   int p, mmax, P, ncoef;
@@ -174,6 +182,7 @@ __global__ __launch_bounds__(1024) void lap_near_kernel(NearLapParams a) {
     oz = a.otab[4 * g + 2];
   }
   const double ctx = a.centres4[4 * t], cty = a.centres4[4 * t + 1], ctz = a.centres4[4 * t + 2];
+  const double at = a.radius ? a.radius[t] : 1.0;
   double v = 0, gx = 0, gy = 0, gz = 0;
   for (int e = s0; e < s1; ++e) {
     const int s = a.near_idx[e];
@@ -181,8 +190,10 @@ __global__ __launch_bounds__(1024) void lap_near_kernel(NearLapParams a) {
     for (int i = threadIdx.x; i < 2 * nc; i += blockDim.x) cs[i] = a.coef[(size_t)s * 2 * nc + i];
     __syncthreads();
     if (!active) continue;
-    laplace_series(a.p, a.mmax, cs, rec, (ctx - a.centres4[4 * s]) + ox, (cty - a.centres4[4 * s + 1]) + oy,
-                   (ctz - a.centres4[4 * s + 2]) + oz, v, gx, gy, gz);
+    const double ias = a.radius ? 1.0 / a.radius[s] : 1.0;
+    laplace_series(a.p, a.mmax, cs, rec, ((ctx - a.centres4[4 * s]) + at * ox) * ias,
+                   ((cty - a.centres4[4 * s + 1]) + at * oy) * ias, ((ctz - a.centres4[4 * s + 2]) + at * oz) * ias, v,
+                   gx, gy, gz);
   }
   if (!active) return;
   const int64_t node = (int64_t)t * a.P + g;
@@ -200,6 +211,7 @@ struct FarLapParams {
   const double* otab;      // P x 4
   const double* centres4;
   const uint32_t* excl;    // nb x nwords
+  const double* radius;    // nb radii, or nullptr for unit spheres
   double* out;             // N: += scale * n . grad   (or nullptr)
   double* grad;            // N x 3: += grad           (or nullptr)
   int64_t N, nb;
@@ -218,6 +230,7 @@ __global__ __launch_bounds__(256) void lap_far_kernel(FarLapParams a) {
   const int t = (int)(xx / a.P);
   const int li = (int)(xx - (int64_t)t * a.P);
   const double ox = a.otab[4 * li], oy = a.otab[4 * li + 1], oz = a.otab[4 * li + 2];
+  const double at = a.radius ? a.radius[t] : 1.0;
   double gx = 0, gy = 0, gz = 0;
   for (int64_t s = 0; s < a.nb; ++s) {
     __syncthreads();
@@ -226,9 +239,11 @@ __global__ __launch_bounds__(256) void lap_far_kernel(FarLapParams a) {
     const bool skip = !valid || ((a.excl[(int64_t)t * a.nwords + (s >> 5)] >> (s & 31)) & 1u);
     if (__any(skip ? 0 : 1) == 0) continue;
     if (skip) continue;
-    const double px = (a.centres4[4 * t] - a.centres4[4 * s]) + ox;
-    const double py = (a.centres4[4 * t + 1] - a.centres4[4 * s + 1]) + oy;
-    const double pz = (a.centres4[4 * t + 2] - a.centres4[4 * s + 2]) + oz;
+    // in units of the source radius (grad S^L is scale-free)
+    const double ias = a.radius ? 1.0 / a.radius[s] : 1.0;
+    const double px = ((a.centres4[4 * t] - a.centres4[4 * s]) + at * ox) * ias;
+    const double py = ((a.centres4[4 * t + 1] - a.centres4[4 * s + 1]) + at * oy) * ias;
+    const double pz = ((a.centres4[4 * t + 2] - a.centres4[4 * s + 2]) + at * oz) * ias;
     double sx = 0, sy = 0, sz = 0;
     for (int i = 0; i < a.P; ++i) {
       const double rx = px - a.otab[4 * i], ry = py - a.otab[4 * i + 1], rz = pz - a.otab[4 * i + 2];
@@ -264,9 +279,11 @@ __global__ void lap_rhs_kernel(const double* otab, int P, int64_t N, double hx, 
   }
 }
 
-// Maxwell traction of H = H0 - grad on each sphere; force and torque (nb x 6).
+// Maxwell traction of H = H0 - grad on each sphere; force and torque (nb x 6); a sphere
+// of radius a: area element a^2, lever arm a n.
 __global__ __launch_bounds__(256) void lap_force_kernel(const double* grad, const double* otab, const double* wnode,
-                                                        int P, double hx, double hy, double hz, double* ft) {
+                                                        const double* radius, int P, double hx, double hy, double hz,
+                                                        double* ft) {
   __shared__ double red[4];
   const int64_t k = blockIdx.x;
   double acc[6] = {0, 0, 0, 0, 0, 0};
@@ -286,12 +303,13 @@ __global__ __launch_bounds__(256) void lap_force_kernel(const double* grad, cons
     acc[5] += nx * ty - ny * tx;
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double rk = radius ? radius[k] : 1.0;
   for (int d = 0; d < 6; ++d) {
     const double v = wsum(acc[d]);
     __syncthreads();
     if (lane == 0) red[wv] = v;
     __syncthreads();
-    if (threadIdx.x == 0) ft[6 * k + d] = red[0] + red[1] + red[2] + red[3];
+    if (threadIdx.x == 0) ft[6 * k + d] = (d < 3 ? rk * rk : rk * rk * rk) * (red[0] + red[1] + red[2] + red[3]);
   }
 }
 
@@ -332,6 +350,7 @@ void launch_others(bie_ctx* c, const double* f, double* out, double* grad, doubl
     a.near_idx = c->dnear_idx.as<int>();
     a.otab = c->otab.as<double>();
     a.rec = c->rec.as<double>();
+    a.radius = c->poly ? c->radius_d.as<double>() : nullptr;
     a.out = out;
     a.grad = grad;
     a.p = c->p;
@@ -349,6 +368,7 @@ void launch_others(bie_ctx* c, const double* f, double* out, double* grad, doubl
   b.otab = c->otab.as<double>();
   b.centres4 = c->centres4.as<double>();
   b.excl = c->excl.as<uint32_t>();
+  b.radius = c->poly ? c->radius_d.as<double>() : nullptr;
   b.out = out;
   b.grad = grad;
   b.N = c->N;
@@ -410,9 +430,9 @@ void solve_magnetic(bie_ctx* c, const double H0[3], double eta, const bie_solve_
   if (o.precond == BIE_PC_MLP) o.precond = BIE_PC_M0;
   *rc = solve(c, OP_LAPLACE, b.as<double>(), q_dev, N, &o, info);
   lap_grad(c, q_dev, grad.as<double>());
-  lap_force_kernel<<<dim3((unsigned)c->nb), dim3(256), 0, c->stream>>>(grad.as<double>(), c->otab.as<double>(),
-                                                                       c->wnode.as<double>(), c->P, H0[0], H0[1],
-                                                                       H0[2], ft.as<double>());
+  lap_force_kernel<<<dim3((unsigned)c->nb), dim3(256), 0, c->stream>>>(
+      grad.as<double>(), c->otab.as<double>(), c->wnode.as<double>(), c->poly ? c->radius_d.as<double>() : nullptr,
+      c->P, H0[0], H0[1], H0[2], ft.as<double>());
   BIE_HIP(hipGetLastError());
   BIE_HIP(hipMemcpyAsync(ft_host, ft.ptr, 6 * c->nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   BIE_HIP(hipStreamSynchronize(c->stream));

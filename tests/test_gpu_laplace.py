@@ -85,3 +85,55 @@ def test_magnetic_forces_match_oracle_and_move_the_spheres():
     d = c[1] - c[0]
     assert np.dot(v[1] - v[0], d) < 0
     s.close()
+
+
+@pytest.fixture(scope="module")
+def poly():
+    # six spheres of radii 0.35-1.4 with near pairs between unequal radii
+    from paper_1707_06551_amd import bie
+    from tests.test_gpu_poly import poly_cluster
+    c, a = poly_cluster()
+    p = 5
+    s = bie.Spheres(c, p, near_gap=1.0, radii=a)
+    g = Geometry(c, p, near_gap=1.0, radii=a)
+    yield c, a, s, g
+    s.close()
+
+
+def test_laplace_operators_with_radii_match_oracle(poly):
+    c, a, s, g = poly
+    assert g.near.sum() > 0
+    lap = laplace.Laplace(g)
+    q = np.random.default_rng(3).standard_normal(g.N)
+    out = host(s.apply_laplace(0, dev(q), eta=0.6))
+    ref = lap.magnetic_bie(q, 0.6)
+    assert rel_err(out, ref) < 1e-11, (rel_err(out, ref), max_rel(out, ref))
+    grad = host(s.apply_laplace(1, dev(q))).reshape(g.N, 3)
+    _v, gref = lap.potential_and_gradient(q)
+    assert rel_err(grad, gref) < 1e-11, (rel_err(grad, gref), max_rel(grad, gref))
+
+
+def test_magnetic_problem_with_radii_matches_oracle(poly):
+    c, a, s, g = poly
+    H0 = np.array([0.3, -0.2, 1.0])
+    F, T, q, info = s.solve_magnetic(H0, 0.5, tol=1e-13, want_q=True)
+    assert info["converged"], info
+    q_ref, F_ref, T_ref, _H = laplace.solve_magnetic(g, H0, 0.5)
+    assert rel_err(host(q), q_ref) < 1e-10
+    assert rel_err(F, F_ref) < 1e-9 and rel_err(T, T_ref) < 1e-8
+
+
+@pytest.mark.parametrize("rad", [0.3, 2.5])
+def test_magnetisable_sphere_of_radius_a(rad):
+    # the density 6 eta / (3 - eta) n . H0 does not depend on the radius; no net load
+    from paper_1707_06551_amd import bie
+    eta = 0.6
+    H0 = np.array([0.2, 0.9, -0.4])
+    s = bie.Spheres(np.array([[1.0, 2.0, 3.0]]), 6, near_gap=1.0, radii=[rad])
+    F, T, q, info = s.solve_magnetic(H0, eta, tol=1e-13, want_q=True)
+    assert info["converged"], info
+    xyz, _w = s.nodes()
+    n = (xyz - np.array([1.0, 2.0, 3.0])) / rad
+    assert np.abs(host(q) - 6 * eta / (3 - eta) * (n @ H0)).max() < 1e-11
+    assert np.abs(F).max() < 1e-11 * rad ** 2 and np.abs(T).max() < 1e-11 * rad ** 3
+    s.close()

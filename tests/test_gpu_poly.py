@@ -338,8 +338,6 @@ def test_polydisperse_rejects_unit_only_features(cluster):
     c, a, s, g = cluster
     mu = dev(np.zeros(3 * g.N))
     with pytest.raises(bie.BieError):
-        s.solve_magnetic([0.0, 0.0, 1.0], 0.5)
-    with pytest.raises(bie.BieError):
         s.apply_precond(bie.OP_SD_BIE, mu, precond=bie.PC_MLP)
     with pytest.raises(bie.BieError):
         bie.Spheres(c, 4, radii=np.full(len(a), 1.2))   # overlapping
