@@ -22,6 +22,14 @@ def small_cluster(n=12, box=9.0, gap=0.15, seed=3):
     return place_spheres(n, box, gap, rng)
 
 
+def poly_cluster():
+    """Six spheres of radii 0.35-1.4, gaps 0.12-0.9 among the near pairs."""
+    c = np.array([[0.0, 0.0, 0.0], [2.2, 0.3, -0.1], [0.4, 1.75, 0.5], [-1.5, -0.6, 0.9],
+                  [1.3, -1.4, 1.2], [4.4, 2.2, 0.4]])
+    a = np.array([1.0, 1.1, 0.45, 0.6, 0.35, 1.4])
+    return c, a
+
+
 def oracle_coef_to_gpu(ops, coef_o, nb):
     """Oracle coefficients (per sphere list of (3, M)) -> GPU layout (nb, 3, ncoef, 2)."""
     g = ops.g
@@ -35,4 +43,4 @@ def oracle_coef_to_gpu(ops, coef_o, nb):
     return out
 
 
-__all__ = ["rel_err", "max_rel", "small_cluster", "oracle_coef_to_gpu", "make_workload"]
+__all__ = ["rel_err", "max_rel", "small_cluster", "poly_cluster", "oracle_coef_to_gpu", "make_workload"]

@@ -5,7 +5,7 @@ import pytest
 
 from oracle import laplace
 from oracle.grid import Geometry
-from tests.gpu_common import max_rel, rel_err, small_cluster
+from tests.gpu_common import max_rel, poly_cluster, rel_err, small_cluster
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -91,7 +91,6 @@ def test_magnetic_forces_match_oracle_and_move_the_spheres():
 def poly():
     # six spheres of radii 0.35-1.4 with near pairs between unequal radii
     from paper_1707_06551_amd import bie
-    from tests.test_gpu_poly import poly_cluster
     c, a = poly_cluster()
     p = 5
     s = bie.Spheres(c, p, near_gap=1.0, radii=a)

@@ -10,7 +10,7 @@ import pytest
 from oracle import rotation_near as rn
 from oracle.grid import Geometry
 from oracle.operators import OPS as ORACLE_OPS, Operators
-from tests.gpu_common import max_rel, rel_err, small_cluster
+from tests.gpu_common import max_rel, poly_cluster, rel_err, small_cluster
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -111,7 +111,6 @@ def poly_case():
     # radii (gaps 0.12-0.9)
     if not _pcase:
         from paper_1707_06551_amd import bie
-        from tests.test_gpu_poly import poly_cluster
         c, a = poly_cluster()
         p = 6
         _pcase["s"] = bie.Spheres(c, p, near_gap=1.0, radii=a, near_method=1)

@@ -10,7 +10,7 @@ from oracle import traction as tr
 from oracle.grid import Geometry
 from oracle.operators import OPS as ORACLE_OPS, Operators
 from oracle.solvers import assemble
-from tests.gpu_common import max_rel, rel_err
+from tests.gpu_common import max_rel, poly_cluster, rel_err
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -25,14 +25,6 @@ def dev(a):
 def host(t):
     torch.cuda.synchronize()
     return t.detach().cpu().numpy()
-
-
-def poly_cluster():
-    """Six spheres of radii 0.35-1.4, gaps 0.12-0.9 among the near pairs."""
-    c = np.array([[0.0, 0.0, 0.0], [2.2, 0.3, -0.1], [0.4, 1.75, 0.5], [-1.5, -0.6, 0.9],
-                  [1.3, -1.4, 1.2], [4.4, 2.2, 0.4]])
-    a = np.array([1.0, 1.1, 0.45, 0.6, 0.35, 1.4])
-    return c, a
 
 
 @pytest.fixture(scope="module")
