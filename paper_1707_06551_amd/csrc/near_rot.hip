@@ -86,12 +86,15 @@ __global__ __launch_bounds__(256) void near_rot_kernel(RotParams a) {
   const int t = blockIdx.x;
   const int p = a.p, mmax = a.mmax, nc = a.ncoef, nl = a.nlat, M1 = mmax + 1;
   const int nfull = (p + 1) * (p + 1);
+  // F (written in step 2, read in 3a) shares B's space (read last in 1c, written again
+  // in 3c); barriers separate those phases
+  const int fb = 6 * nfull > 6 * nl * M1 ? 6 * nfull : 6 * nl * M1;
   double* A = sm;                      // 3 x nfull x 2, order k = n^2 + m + n
   double* B = A + 6 * nfull;           // 3 x nfull x 2
-  double* U = B + 6 * nfull;           // 3 x nc x 2, slot layout
+  double* F = B;                       // 3 x nl x M1 x 2
+  double* U = B + fb;                  // 3 x nc x 2, slot layout
   double* ACC = U + 6 * nc;            // 3 x nc x 2
-  double* F = ACC + 6 * nc;            // 3 x nl x M1 x 2
-  double* rec = F + 6 * nl * M1;       // nc x 6
+  double* rec = ACC + 6 * nc;          // nc x 6
   double* ca = rec + 6 * nc;           // cos(m a), sin(m a), cos(m b), sin(m b), m = 0..p
   double* sa = ca + (p + 1);
   double* cb = sa + (p + 1);
@@ -297,8 +300,8 @@ __global__ __launch_bounds__(256) void near_rot_kernel(RotParams a) {
 
 static size_t rot_smem(const bie_ctx* c) {
   const size_t nfull = (size_t)(c->p + 1) * (c->p + 1);
-  return sizeof(double) *
-         (12 * nfull + 18 * (size_t)c->ncoef + 6 * (size_t)c->nlat * (c->mmax + 1) + 4 * (c->p + 1) + 4 * 33);
+  const size_t fb = std::max(6 * nfull, 6 * (size_t)c->nlat * (c->mmax + 1));   // B and F share it
+  return sizeof(double) * (6 * nfull + fb + 18 * (size_t)c->ncoef + 4 * (c->p + 1) + 4 * 33);
 }
 
 void launch_near_rot(bie_ctx* c, const OpSpec& spec, double* u) {
