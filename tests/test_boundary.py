@@ -57,3 +57,14 @@ def test_native_sources_do_not_reference_the_oracle():
             glob.glob(os.path.join(ROOT, "include", "*.h")):
         text = open(path, encoding="utf-8").read()
         assert "oracle" not in text.lower(), path
+
+
+def test_product_path_fails_loudly_without_the_library(monkeypatch):
+    # no fallback: with libbie.so absent the binding raises before any work is done
+    import pytest
+
+    from paper_1707_06551_amd import bie
+    monkeypatch.setattr(bie, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libbie.so"))
+    monkeypatch.setattr(bie, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        bie.lib()
