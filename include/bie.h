@@ -1,11 +1,12 @@
 /*
- * bie.h - C ABI of the MI355X boundary-integral library for suspensions of unit spheres
- * in Stokes flow (Corona & Veerapaneni, "Boundary integral equation analysis for
+ * bie.h - C ABI of the MI355X boundary-integral library for suspensions of spheres in
+ * Stokes flow (Corona & Veerapaneni, "Boundary integral equation analysis for
  * suspension of spheres in Stokes flow", arXiv:1707.06551).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
- * - Viscosity 1 (Section 5).  All spheres have radius 1.
+ * - Viscosity 1 (Section 5).  Spheres have radius 1 (bie_build_spheres) unless built
+ *   with bie_build_spheres_radii, whose comment states what changes with a radius.
  * - Grid (Eq. 4.2): p+1 Gauss-Legendre latitudes (theta ascending) x n_phi uniform
  *   longitudes phi_l = 2 pi l / n_phi.  P = (p+1) n_phi nodes per sphere, N = n_b P.
  *   Node order: g = k*P + j*n_phi + l (sphere k, latitude j, longitude l).
