@@ -1,0 +1,66 @@
+"""Degenerate and boundary cases of the C ABI on the GPU: overlapping spheres, a lone
+sphere (no pairs at all), a near-touching pair, and field evaluation with no targets."""
+import numpy as np
+import pytest
+
+from oracle.grid import Geometry
+from oracle.operators import Operators
+from tests.gpu_common import rel_err
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).reshape(-1)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def test_overlapping_unit_spheres_are_rejected():
+    from paper_1707_06551_amd import bie
+    with pytest.raises(bie.BieError) as e:
+        bie.Spheres(np.array([[0.0, 0.0, 0.0], [1.9, 0.0, 0.0]]), 4)
+    assert e.value.code == bie.EOVERLAP
+
+
+def test_lone_sphere_has_no_near_or_far_part():
+    from paper_1707_06551_amd import bie
+    s = bie.Spheres(np.array([[0.5, -0.3, 2.0]]), 6, near_gap=1.0)
+    assert s.near_pairs().shape[1] == 0
+    mu = dev(np.random.default_rng(1).standard_normal(3 * s.N))
+    for stage in (bie.STAGE_NEAR, bie.STAGE_FAR):
+        for prec in (bie.FP64, bie.MIXED):
+            out = host(s.apply(bie.OP_SD_BIE | stage, mu, precision=prec))
+            assert np.all(out == 0.0), (stage, prec)
+    s.close()
+
+
+def test_near_touching_pair_matches_oracle():
+    # surface gap 1e-3: the near series at a neighbour almost in contact (convergent,
+    # slowly, at the closest nodes), float64 against the oracle
+    from paper_1707_06551_amd import bie
+    c = np.array([[0.0, 0.0, 0.0], [0.6, 1.2, 1.5]])
+    c[1] *= 2.001 / np.linalg.norm(c[1])
+    p = 8
+    s = bie.Spheres(c, p, near_gap=1.0)
+    g = Geometry(c, p, near_gap=1.0)
+    ops = Operators(g)
+    mu = np.random.default_rng(2).standard_normal((g.N, 3))
+    out = host(s.apply(bie.OP_SD_BIE, dev(mu))).reshape(g.N, 3)
+    ref = ops.apply("SD_BIE", mu)
+    assert np.isfinite(out).all()
+    assert rel_err(out, ref) < 1e-11, rel_err(out, ref)
+    s.close()
+
+
+def test_field_evaluation_with_no_targets_is_a_noop():
+    from paper_1707_06551_amd import bie
+    s = bie.Spheres(np.array([[0.0, 0.0, 0.0], [3.0, 0.0, 0.0]]), 4, near_gap=1.0)
+    mu = dev(np.ones(3 * s.N))
+    u = s.eval_field(bie.OP_SD_BIE, mu, np.zeros((0, 3)))
+    assert u.numel() == 0
+    s.close()
