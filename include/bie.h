@@ -79,7 +79,10 @@ typedef struct bie_ctx bie_ctx;
 typedef struct {
   int p;             /* SH order, 1 <= p <= 20                                           */
   int n_phi;         /* azimuthal nodes; 0 selects 2p; must be even and >= 2p            */
-  double near_gap;   /* surface-gap threshold d* of Eq. 4.5; <= 0 selects 1.0            */
+  double near_gap;   /* surface-gap threshold d* of Eq. 4.5 (spheres t != s are near when
+                        |c_t - c_s| - 2 < d*); > 0: taken as given (finite);  <= 0: d* is
+                        measured for this grid at the precision near_tol, see
+                        bie_near_gap_for                                                 */
   int device;        /* HIP device ordinal                                               */
   void* hip_stream;  /* hipStream_t for all device work (NULL = default stream)          */
   int near_method;   /* near-pair evaluation: 0 = exterior series at the target nodes
@@ -94,7 +97,24 @@ typedef struct {
                         in float32 / float64, one tile per order m and row block of 16).
                         Same results up to rounding order; 0 is faster at every measured
                         size (the stage is latency-bound).  0 or 1, BIE_EINVAL otherwise */
+  double near_tol;   /* precision that selects d* when near_gap <= 0 (Eq. 4.5: eta is set
+                        from the user's precision); <= 0 selects 1e-8, NaN is BIE_EINVAL.
+                        Ignored when near_gap > 0                                        */
 } bie_opts;
+
+/* The separation threshold d* of Eq. 4.5 (a surface gap, d* = 2 eta for unit spheres)
+ * that the grid of order p on n_phi longitudes (0 selects 2p) needs for precision tol in
+ * (0, 1): the smallest gap of the grid g_k = 2^(k/8) / 64 (k = 0..104) at which the smooth
+ * quadrature of Eq. 4.4 stays within tol / 10 of the exact exterior potentials (Eqs.
+ * 3.6-3.11) of the single and the double layer, measured as in the paper's Section 6
+ * test (Fig. 5): two random densities of degree <= p with flat spectra (coefficients
+ * uniform on [-1, 1) from a counter-based SplitMix64 stream), 256 targets on a shell of
+ * radius 1 + g, the error against the density's largest nodal value.  The search walks
+ * the grid down from g = 128 in steps of 8 and then of 1 while the error passes.  Writes
+ * +infinity (every pair near) when g = 128 already fails.  Host computation only (no
+ * device use; results are cached per (p, n_phi, tol)); BIE_EINVAL for p outside [1, 20],
+ * a bad n_phi or tol outside (0, 1). */
+int bie_near_gap_for(int p, int n_phi, double tol, double* d_star);
 
 /* Builds the discretisation for n_spheres unit spheres (Eq. 4.2 grid, Legendre and
  * Fourier tables, eigenvalue tables of Table 3.12, near-pair lists of Eq. 4.5) and
@@ -129,8 +149,17 @@ int bie_build_spheres_radii(const double* centres, const double* radii, int64_t 
 
 void bie_free(bie_ctx* ctx);
 
-/* Number of nodes N; number of spheres; P per sphere; mmax.  Host outputs. */
+/* Number of nodes N; number of spheres; P per sphere; mmax.  Host outputs, each
+ * optional. */
 int bie_sizes(const bie_ctx* ctx, int64_t* n_nodes, int64_t* n_spheres, int64_t* nodes_per_sphere, int64_t* mmax);
+
+/* Number of nodes N = n_b (p + 1) n_phi of the grid of Eq. 4.2 (host output). */
+int bie_num_nodes(const bie_ctx* ctx, int64_t* n_nodes);
+
+/* The context's separation threshold d* of Eq. 4.5 (+infinity: every pair near) and the
+ * precision it was measured for (0 when near_gap was given).  Host outputs, each
+ * optional. */
+int bie_near_gap(const bie_ctx* ctx, double* d_star, double* near_tol);
 
 /* Node coordinates (N x 3) and quadrature weights (N, Eq. 4.4) in ABI node order.
  * Host outputs; either pointer may be NULL. */
@@ -287,13 +316,15 @@ int bie_solve_magnetic(bie_ctx* ctx, const double* H0, double eta, const bie_sol
  *   s x,  a - 3 (a.x) x,  b,  c x x,  2 T x - 5 (x.T x) x,  2 T x,  2 x x (T x),
  * x the unit normal, T = sum_k t_k E_k over the Frobenius-orthonormal symmetric
  * traceless basis (xy, yz, xz, xx - yy, 2zz - xx - yy).  BIE_PC_MLP applies
- *   z = M0 r + P zeta,  zeta_i = sum_{j near i} rot_ij^T [K_off rot_ij rho_j + K_self rot_ij rho_i],
+ *   z = M0 r + P zeta,  zeta_i = sum_{j close to i} rot_ij^T [K_off rot_ij rho_j + K_self rot_ij rho_i],
  * rho = R r (weighted projection with the Eq. 4.4 weights), P = synthesis, rot_ij the
  * rotation into the frame whose z axis points from c_i to c_j, and K(theta) 25 x 25
  * maps commuting with rotations about that axis (139 parameters each) produced per
- * directed near pair by an MLP (8 -> 64 -> 64 -> 278, tanh, float32) of the pair's
- * features: gap g, log(g + 0.01), 0.1/(g + 0.1), near counts of i and j / 8, smallest
- * other gap of i and of j (near_gap if none), sum_{k near i} 0.1/(g_ik + 0.1).
+ * directed close pair by an MLP (8 -> 64 -> 64 -> 278, tanh, float32) of the pair's
+ * features: gap g, log(g + 0.01), 0.1/(g + 0.1), close counts of i and j / 8, smallest
+ * other gap of i and of j (1 if none), sum_{k close to i} 0.1/(g_ik + 0.1).  Close pairs
+ * are those with surface gap |c_i - c_j| - 2 < 1, the gap the network was trained
+ * with; they do not depend on the context's d*.
  * The correction acts on the density part of the resistance and mobility forms (the
  * network is trained per form: weights/precond_dn*.npz, weights/precond_mob.npz); for
  * BIE_OP_SD_BIE BIE_PC_MLP is M0. */
@@ -303,7 +334,7 @@ int bie_lowmodes(bie_ctx* ctx, const double* f, double* rho);
 /* f = P rho (overwrites f). */
 int bie_lowmodes_synth(bie_ctx* ctx, const double* rho, double* f);
 
-/* Directed near pairs in CSR order (grouped by target sphere i), with features and
+/* Directed close pairs (surface gap < 1) in CSR order (grouped by target sphere i), with features and
  * frames.  Host outputs, each optional: pair_i, pair_j (count), feats (count x 8),
  * frames (count x 34: Q row-major then D2 row-major, D2_kl = tr(E_k Q E_l Q^T)). */
 int bie_pair_geometry(const bie_ctx* ctx, int64_t* count, int32_t* pair_i, int32_t* pair_j, float* feats,
@@ -313,7 +344,7 @@ int bie_pair_geometry(const bie_ctx* ctx, int64_t* count, int32_t* pair_i, int32
 int64_t bie_mlp_n_weights(void);
 
 /* Loads MLP weights (host, float32) into the context and evaluates theta for every
- * directed near pair on the device; enables BIE_PC_MLP.  Rejects non-finite weights. */
+ * directed close pair on the device; enables BIE_PC_MLP.  Rejects non-finite weights. */
 int bie_precond_load(bie_ctx* ctx, const float* weights, int64_t n_weights);
 
 /* Training set for the MLP: n_configs configurations concatenated; spheres and pairs

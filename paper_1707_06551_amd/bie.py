@@ -27,6 +27,7 @@ EXPORTED = [
     "bie_solve", "bie_apply_precond", "bie_lowmodes", "bie_lowmodes_synth", "bie_pair_geometry",
     "bie_mlp_n_weights", "bie_precond_load", "bie_mlp_eval", "bie_mlp_train", "bie_eval_field",
     "bie_apply_laplace", "bie_solve_magnetic", "bie_solve_mobility_traction", "bie_build_spheres_radii",
+    "bie_num_nodes", "bie_near_gap", "bie_near_gap_for",
 ]
 NLOW = 25
 NFEAT = 8
@@ -44,7 +45,7 @@ class MlpData(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int), ("n_phi", ctypes.c_int), ("near_gap", ctypes.c_double),
                 ("device", ctypes.c_int), ("hip_stream", ctypes.c_void_p), ("near_method", ctypes.c_int),
-                ("legendre_mfma", ctypes.c_int)]
+                ("legendre_mfma", ctypes.c_int), ("near_tol", ctypes.c_double)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -81,6 +82,12 @@ def lib():
     L.bie_free.restype = None
     L.bie_sizes.argtypes = [VP, P(I64), P(I64), P(I64), P(I64)]
     L.bie_sizes.restype = I
+    L.bie_num_nodes.argtypes = [VP, P(I64)]
+    L.bie_num_nodes.restype = I
+    L.bie_near_gap.argtypes = [VP, P(D), P(D)]
+    L.bie_near_gap.restype = I
+    L.bie_near_gap_for.argtypes = [I, I, D, P(D)]
+    L.bie_near_gap_for.restype = I
     L.bie_get_nodes.argtypes = [VP, VP, VP]
     L.bie_get_nodes.restype = I
     L.bie_near_pairs.argtypes = [VP, P(I64), VP]
@@ -129,6 +136,13 @@ def lib():
 
 def mlp_n_weights():
     return int(lib().bie_mlp_n_weights())
+
+
+def near_gap_for(p, tol, n_phi=0):
+    """d* of Eq. 4.5 for grid order p and precision tol (bie_near_gap_for; host only)."""
+    d = ctypes.c_double()
+    _check(lib().bie_near_gap_for(p, n_phi, tol, ctypes.byref(d)))
+    return d.value
 
 
 class TrainingSet:
@@ -212,10 +226,12 @@ def _dptr(t):
 class Spheres:
     """A context for n_b spheres (bie_build_spheres; bie_build_spheres_radii when radii
     are given: polydisperse suspensions, a subset of the operators).  legendre_mfma = 1
-    runs the transforms' Legendre stages on the matrix cores (bie_opts.legendre_mfma)."""
+    runs the transforms' Legendre stages on the matrix cores (bie_opts.legendre_mfma).
+    near_gap = None (or <= 0) measures d* of Eq. 4.5 for the precision near_tol
+    (None: the library's default, 1e-8); a positive near_gap is taken as given."""
 
-    def __init__(self, centres, p, n_phi=0, near_gap=1.0, device=0, stream=None, near_method=0, radii=None,
-                 legendre_mfma=0):
+    def __init__(self, centres, p, n_phi=0, near_gap=None, device=0, stream=None, near_method=0, radii=None,
+                 legendre_mfma=0, near_tol=None):
         import torch
         L = lib()
         c = np.ascontiguousarray(centres, dtype=np.float64).reshape(-1, 3)
@@ -223,7 +239,8 @@ class Spheres:
             stream = torch.cuda.current_stream(device)
         self.stream = stream
         self.device = device
-        o = Opts(p, n_phi, near_gap, device, ctypes.c_void_p(stream.cuda_stream), near_method, legendre_mfma)
+        o = Opts(p, n_phi, 0.0 if near_gap is None else near_gap, device, ctypes.c_void_p(stream.cuda_stream),
+                 near_method, legendre_mfma, 0.0 if near_tol is None else near_tol)
         h = ctypes.c_void_p()
         if radii is None:
             _check(L.bie_build_spheres(_hptr(c), c.shape[0], ctypes.byref(o), ctypes.byref(h)))
@@ -237,6 +254,9 @@ class Spheres:
         _check(L.bie_sizes(h, ctypes.byref(n), ctypes.byref(nb), ctypes.byref(P), ctypes.byref(mm)))
         self.N, self.nb, self.P, self.mmax, self.p = n.value, nb.value, P.value, mm.value, p
         self.ncoef = sum(p + 1 - m for m in range(self.mmax + 1))
+        d, t = ctypes.c_double(), ctypes.c_double()
+        _check(L.bie_near_gap(h, ctypes.byref(d), ctypes.byref(t)))
+        self.near_gap, self.near_tol = d.value, t.value
 
     def close(self):
         if getattr(self, "_h", None):

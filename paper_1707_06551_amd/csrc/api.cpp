@@ -322,6 +322,28 @@ int bie_sizes(const bie_ctx* c, int64_t* n_nodes, int64_t* n_spheres, int64_t* n
   return BIE_OK;
 }
 
+int bie_num_nodes(const bie_ctx* c, int64_t* n_nodes) {
+  if (!c || !n_nodes) return BIE_EINVAL;
+  *n_nodes = c->N;
+  return BIE_OK;
+}
+
+int bie_near_gap(const bie_ctx* c, double* d_star, double* near_tol) {
+  if (!c) return BIE_EINVAL;
+  if (d_star) *d_star = c->near_gap;
+  if (near_tol) *near_tol = c->near_tol;
+  return BIE_OK;
+}
+
+int bie_near_gap_for(int p, int n_phi, double tol, double* d_star) {
+  if (!d_star) {
+    bie::set_error("d_star is NULL");
+    return BIE_EINVAL;
+  }
+  BIE_TRY(*d_star = bie::near_gap_for(p, n_phi, tol));
+  return BIE_OK;
+}
+
 int bie_get_nodes(const bie_ctx* c, double* xyz, double* w) {
   if (!c) return BIE_EINVAL;
   for (int64_t k = 0; k < c->nb; ++k)
@@ -622,12 +644,12 @@ int bie_lowmodes_synth(bie_ctx* c, const double* rho, double* f) {
 int bie_pair_geometry(const bie_ctx* c, int64_t* count, int32_t* pair_i, int32_t* pair_j, float* feats,
                       double* frames) {
   if (!c || !count) return BIE_EINVAL;
-  const int64_t np = (int64_t)c->near_idx.size();
+  const int64_t np = (int64_t)c->close_idx.size();
   *count = np;
   for (int64_t i = 0; i < c->nb; ++i)
-    for (int e = c->near_ptr[i]; e < c->near_ptr[i + 1]; ++e) {
+    for (int e = c->close_ptr[i]; e < c->close_ptr[i + 1]; ++e) {
       if (pair_i) pair_i[e] = (int32_t)i;
-      if (pair_j) pair_j[e] = c->near_idx[e];
+      if (pair_j) pair_j[e] = c->close_idx[e];
     }
   if (feats && np) std::memcpy(feats, c->pair_feat.data(), c->pair_feat.size() * sizeof(float));
   if (frames && np) std::memcpy(frames, c->pair_frame.data(), c->pair_frame.size() * sizeof(double));

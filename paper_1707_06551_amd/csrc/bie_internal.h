@@ -56,7 +56,8 @@ struct bie_ctx {
   // discretisation
   int p = 0, n_phi = 0, mmax = 0, P = 0, ncoef = 0, nlat = 0;
   int64_t nb = 0, N = 0;
-  double near_gap = 1.0;
+  double near_gap = 1.0;   // d* of Eq. 4.5 (+infinity: every pair near)
+  double near_tol = 0.0;   // precision d* was calibrated for (0 when near_gap was given)
   int device = 0;
   hipStream_t stream = nullptr;
 
@@ -66,6 +67,10 @@ struct bie_ctx {
   bool poly = false;            // some radius differs from 1
   std::vector<double> t, lam, theta, wlat, phi;
   std::vector<int> near_ptr, near_idx;  // CSR, target sphere -> near source spheres
+  // close pairs of the learned correction: surface gap below close_gap (the gap its
+  // network was trained with), independent of d*
+  double close_gap = 1.0;
+  std::vector<int> close_ptr, close_idx;
   std::vector<int> coef_m, coef_n, coef_off;  // mode (m, n) of each coefficient slot; slot of (m, m)
 
   // device: geometry
@@ -74,6 +79,7 @@ struct bie_ctx {
   bie::DevBuf excl;       // nb x nwords uint32: bit s of row t set if s == t or (t, s) near
   int nwords = 0;
   bie::DevBuf dnear_ptr, dnear_idx;
+  bie::DevBuf dclose_ptr, dclose_idx;
   bie::DevBuf otab, otab_f;    // P x 4 unit offsets of the nodes of a sphere (double / float)
   bie::DevBuf osrc, osrc_f;    // P x 4 the same offsets times -2 (far-field source table)
   bie::DevBuf frame;           // P x 9 double: e_r, e_theta, e_phi at each node
@@ -162,6 +168,18 @@ void launch_near_rot(bie_ctx* c, const OpSpec& spec, double* u);
 void series_radial(double a_s, double a_d, int p, double* kvv, double* kww, double* kwv, double* kxx);
 void launch_far(bie_ctx* c, int precision, const OpSpec& spec, double* u);
 void apply(bie_ctx* c, int op, int precision, const double* mu, double* u);
+
+// Set-up helpers (setup.cpp): Gauss-Legendre rule (nodes descending), Legendre tables
+// at one latitude per coefficient slot (Pbar, dPbar/dtheta, m Pbar / sin theta), the
+// recurrence table of the series evaluations (series.h).
+void gauss_legendre(int n, std::vector<double>& t, std::vector<double>& w);
+void legendre_tables(int p, int mmax, double t, double s, const std::vector<int>& cm, const std::vector<int>& cn,
+                     double* outP, double* outD, double* outQ);
+std::vector<double> recurrence_table(int p, int mmax);
+// d* of Eq. 4.5 for grid order p on n_phi longitudes and precision tol (calibrate.cpp);
+// +infinity when no gap of the search range reaches it
+double near_gap_for(int p, int n_phi, double tol);
+constexpr double kDefaultNearTol = 1e-8;
 
 // Small BLAS-1 helpers on device vectors (float64), stream-ordered on c->stream.
 void dev_dot_many(bie_ctx* c, const double* V, int64_t ld, int k, const double* w, int64_t n, double* host_out);

@@ -116,8 +116,8 @@ void build_coarse(bie_ctx* c) {
   BIE_HIP(hipMemcpy(c->lowF.ptr, F.data(), F.size() * sizeof(double), hipMemcpyHostToDevice));
   c->lownorm.alloc(25 * sizeof(double));
   BIE_HIP(hipMemcpy(c->lownorm.ptr, nrm.data(), 25 * sizeof(double), hipMemcpyHostToDevice));
-  // directed near pairs grouped by target sphere: features and frames
-  const int64_t np = (int64_t)c->near_idx.size();
+  // directed close pairs grouped by target sphere: features and frames
+  const int64_t np = (int64_t)c->close_idx.size();
   c->pair_feat.assign((size_t)np * kNFeat, 0.0f);
   c->pair_frame.assign((size_t)np * kFrame, 0.0);
   const double* ce = c->centres.data();
@@ -126,24 +126,24 @@ void build_coarse(bie_ctx* c) {
     return std::sqrt(dx * dx + dy * dy + dz * dz) - 2.0;
   };
   for (int64_t i = 0; i < c->nb; ++i) {
-    const int ni = c->near_ptr[i + 1] - c->near_ptr[i];
+    const int ni = c->close_ptr[i + 1] - c->close_ptr[i];
     double crowd = 0.0;
-    for (int e = c->near_ptr[i]; e < c->near_ptr[i + 1]; ++e) crowd += 0.1 / (gap((int)i, c->near_idx[e]) + 0.1);
-    for (int e = c->near_ptr[i]; e < c->near_ptr[i + 1]; ++e) {
-      const int j = c->near_idx[e];
-      const int nj = c->near_ptr[j + 1] - c->near_ptr[j];
+    for (int e = c->close_ptr[i]; e < c->close_ptr[i + 1]; ++e) crowd += 0.1 / (gap((int)i, c->close_idx[e]) + 0.1);
+    for (int e = c->close_ptr[i]; e < c->close_ptr[i + 1]; ++e) {
+      const int j = c->close_idx[e];
+      const int nj = c->close_ptr[j + 1] - c->close_ptr[j];
       const double g = gap((int)i, j);
-      double mi = c->near_gap, mj = c->near_gap;
+      double mi = c->close_gap, mj = c->close_gap;
       bool hi = false, hj = false;
-      for (int q = c->near_ptr[i]; q < c->near_ptr[i + 1]; ++q)
-        if (c->near_idx[q] != j) {
-          const double gg = gap((int)i, c->near_idx[q]);
+      for (int q = c->close_ptr[i]; q < c->close_ptr[i + 1]; ++q)
+        if (c->close_idx[q] != j) {
+          const double gg = gap((int)i, c->close_idx[q]);
           mi = hi ? std::min(mi, gg) : gg;
           hi = true;
         }
-      for (int q = c->near_ptr[j]; q < c->near_ptr[j + 1]; ++q)
-        if (c->near_idx[q] != (int)i) {
-          const double gg = gap(j, c->near_idx[q]);
+      for (int q = c->close_ptr[j]; q < c->close_ptr[j + 1]; ++q)
+        if (c->close_idx[q] != (int)i) {
+          const double gg = gap(j, c->close_idx[q]);
           mj = hj ? std::min(mj, gg) : gg;
           hj = true;
         }
@@ -210,16 +210,16 @@ __global__ void k_prolong(const double* rho, const double* F, int P, int64_t N, 
   }
 }
 
-// zeta_i = sum_{e in near(i)} rot_e^T [K_off(theta_e) rot_e rho_j + K_self(theta_e) rot_e rho_i]
-__global__ void k_coarse_apply(const double* rho, const int* near_ptr, const int* near_idx, const double* frames,
+// zeta_i = sum_{e in close(i)} rot_e^T [K_off(theta_e) rot_e rho_j + K_self(theta_e) rot_e rho_i]
+__global__ void k_coarse_apply(const double* rho, const int* close_ptr, const int* close_idx, const double* frames,
                                const float* theta, int64_t nb, double* zeta) {
   const int64_t sph = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (sph >= nb) return;
   double z[25];
   for (int m = 0; m < 25; ++m) z[m] = 0.0;
   const double* ri = rho + (int64_t)sph * 25;
-  for (int e = near_ptr[sph]; e < near_ptr[sph + 1]; ++e) {
-    const int j = near_idx[e];
+  for (int e = close_ptr[sph]; e < close_ptr[sph + 1]; ++e) {
+    const int j = close_idx[e];
     const double* fr = frames + (size_t)e * kFrame;
     double y[25], x[25], c[25], back[25];
     rot25_apply<double>(fr, rho + (int64_t)j * 25, y, false);
@@ -247,10 +247,10 @@ void lowmode_prolong(bie_ctx* c, const double* rho, double* f, bool accumulate) 
 
 // z += P zeta(R r): the learned part of the MLP preconditioner (z already holds M0 r)
 void coarse_correct(bie_ctx* c, const double* r, double* z) {
-  if (!c->theta_ready || c->near_idx.empty()) return;
+  if (!c->theta_ready || c->close_idx.empty()) return;
   lowmode_restrict(c, r, c->rho.as<double>());
   k_coarse_apply<<<dim3((unsigned)((c->nb + 63) / 64)), dim3(64), 0, c->stream>>>(
-      c->rho.as<double>(), c->dnear_ptr.as<int>(), c->dnear_idx.as<int>(), c->dframe.as<double>(),
+      c->rho.as<double>(), c->dclose_ptr.as<int>(), c->dclose_idx.as<int>(), c->dframe.as<double>(),
       c->mlp_theta.as<float>(), c->nb, c->zeta.as<double>());
   BIE_HIP(hipGetLastError());
   lowmode_prolong(c, c->zeta.as<double>(), z, true);

@@ -372,9 +372,9 @@ void mlp_train(const bie_mlp_data* d, float* weights, int epochs, int cfg_per_ba
   BIE_HIP(hipMemcpy(weights, net.w.p, kNW * sizeof(float), hipMemcpyDeviceToHost));
 }
 
-// Inference on a context: theta for every directed near pair from the stored features.
+// Inference on a context: theta for every directed close pair from the stored features.
 void mlp_infer(bie_ctx* c, const float* weights) {
-  const int64_t np = (int64_t)c->near_idx.size();
+  const int64_t np = (int64_t)c->close_idx.size();
   c->mlp_theta.alloc((size_t)std::max<int64_t>(1, np) * kNTheta2 * sizeof(float));
   c->theta_ready = false;
   if (np == 0) {

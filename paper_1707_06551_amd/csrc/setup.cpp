@@ -48,7 +48,7 @@ OpSpec op_spec(int op_base) {
 
 // Gauss-Legendre nodes (descending) and weights on [-1, 1] by Newton's method on
 // P_n, with the three-term recurrence for P_n and its derivative.
-static void gauss_legendre(int n, std::vector<double>& t, std::vector<double>& w) {
+void gauss_legendre(int n, std::vector<double>& t, std::vector<double>& w) {
   t.assign(n, 0.0);
   w.assign(n, 0.0);
   for (int i = 0; i < n; ++i) {
@@ -245,7 +245,16 @@ void build(bie_ctx* c, const double* centres, const double* radii, int64_t nb, c
   c->P = c->nlat * nphi;
   c->nb = nb;
   c->N = nb * c->P;
-  c->near_gap = o->near_gap > 0 ? o->near_gap : 1.0;
+  // d* of Eq. 4.5: given, or measured for this grid at the requested precision
+  if (!(o->near_gap <= 0.0 || std::isfinite(o->near_gap))) throw Error{BIE_EINVAL, "near_gap must be finite"};
+  if (std::isnan(o->near_tol)) throw Error{BIE_EINVAL, "near_tol is NaN"};
+  if (o->near_gap > 0) {
+    c->near_gap = o->near_gap;
+    c->near_tol = 0.0;
+  } else {
+    c->near_tol = o->near_tol > 0 ? o->near_tol : kDefaultNearTol;
+    c->near_gap = near_gap_for(o->p, nphi, c->near_tol);
+  }
   if (o->near_method != 0 && o->near_method != 1) throw Error{BIE_EINVAL, "near_method must be 0 or 1"};
   c->near_method = o->near_method;
   if (o->legendre_mfma != 0 && o->legendre_mfma != 1) throw Error{BIE_EINVAL, "legendre_mfma must be 0 or 1"};
@@ -274,24 +283,37 @@ void build(bie_ctx* c, const double* centres, const double* radii, int64_t nb, c
 
   // ---- near pairs (Eq. 4.5 as a surface-gap test) with a uniform cell list --------
   // unit spheres: near when |c_t - c_s| - 2 < d*; radii a: when the gap
-  // |c_t - c_s| - a_t - a_s is below d* a_s (the source's own length scale)
-  const double cut = (2.0 + c->near_gap) * amax;
-  const double cut2 = cut * cut;
-  double lo[3] = {1e300, 1e300, 1e300};
+  // |c_t - c_s| - a_t - a_s is below d* a_s (the source's own length scale).  Close pairs
+  // of the learned correction: |c_t - c_s| - 2 < close_gap (unit spheres).  An infinite
+  // d* makes every pair near: one cell holds every sphere.
+  const bool all_near = !std::isfinite(c->near_gap);
+  const double reach = all_near ? 0.0 : std::max(c->near_gap, c->close_gap);
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
   for (int64_t k = 0; k < nb; ++k)
-    for (int d = 0; d < 3; ++d) lo[d] = std::min(lo[d], centres[3 * k + d]);
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = std::min(lo[d], centres[3 * k + d]);
+      hi[d] = std::max(hi[d], centres[3 * k + d]);
+    }
+  double cut = (2.0 + reach) * amax;
+  // a cell at least 2 a_max wide (overlap test) and at most 2^20 cells per axis
+  for (int d = 0; d < 3; ++d) cut = std::max(cut, (hi[d] - lo[d]) / 1048576.0);
+  if (all_near) cut = 1e300;
   std::unordered_map<int64_t, std::vector<int>> cells;
   auto key = [](int64_t a, int64_t b, int64_t d) { return (a * 2097152 + b) * 2097152 + d; };
   std::vector<int64_t> cidx(3 * nb);
   for (int64_t k = 0; k < nb; ++k) {
-    for (int d = 0; d < 3; ++d) cidx[3 * k + d] = (int64_t)std::floor((centres[3 * k + d] - lo[d]) / cut);
+    for (int d = 0; d < 3; ++d)
+      cidx[3 * k + d] = all_near ? 0 : (int64_t)std::floor((centres[3 * k + d] - lo[d]) / cut);
     cells[key(cidx[3 * k], cidx[3 * k + 1], cidx[3 * k + 2])].push_back((int)k);
   }
-  std::vector<std::vector<int>> nbr(nb);
+  const double ccut = (2.0 + c->close_gap) * (2.0 + c->close_gap);
+  std::vector<std::vector<int>> nbr(nb), cls(nb);
+  int64_t total = 0;
   for (int64_t k = 0; k < nb; ++k) {
     for (int dx = -1; dx <= 1; ++dx)
       for (int dy = -1; dy <= 1; ++dy)
         for (int dz = -1; dz <= 1; ++dz) {
+          if (all_near && (dx || dy || dz)) continue;
           auto it = cells.find(key(cidx[3 * k] + dx, cidx[3 * k + 1] + dy, cidx[3 * k + 2] + dz));
           if (it == cells.end()) continue;
           for (int s : it->second) {
@@ -303,20 +325,27 @@ void build(bie_ctx* c, const double* centres, const double* radii, int64_t nb, c
             const double rs = rad[k] + rad[s];
             if (d2 < rs * rs)
               throw Error{BIE_EOVERLAP, "spheres " + std::to_string(k) + " and " + std::to_string(s) + " overlap"};
-            if (!c->poly) {
-              if (d2 < cut2) nbr[k].push_back(s);
-            } else if (std::sqrt(d2) - rs < c->near_gap * rad[s]) {
-              nbr[k].push_back(s);
-            }
+            if (!c->poly && d2 < ccut) cls[k].push_back(s);
+            if (all_near || std::sqrt(d2) - rs < c->near_gap * rad[s]) nbr[k].push_back(s);
           }
         }
     std::sort(nbr[k].begin(), nbr[k].end());
+    std::sort(cls[k].begin(), cls[k].end());
+    total += (int64_t)nbr[k].size();
+    if (total > 2000000000)
+      throw Error{BIE_EINVAL, "more than 2e9 near pairs at d* = " + std::to_string(c->near_gap) +
+                                  ": ask for a larger near_tol or give near_gap"};
   }
   c->near_ptr.assign(nb + 1, 0);
   c->near_idx.clear();
+  c->near_idx.reserve((size_t)total);
+  c->close_ptr.assign(nb + 1, 0);
+  c->close_idx.clear();
   for (int64_t k = 0; k < nb; ++k) {
     c->near_idx.insert(c->near_idx.end(), nbr[k].begin(), nbr[k].end());
     c->near_ptr[k + 1] = (int)c->near_idx.size();
+    c->close_idx.insert(c->close_idx.end(), cls[k].begin(), cls[k].end());
+    c->close_ptr[k + 1] = (int)c->close_idx.size();
   }
   c->nwords = (int)((nb + 31) / 32);
   std::vector<uint32_t> ex((size_t)nb * c->nwords, 0u);
@@ -414,6 +443,8 @@ void build(bie_ctx* c, const double* centres, const double* radii, int64_t nb, c
   upload_vec(c->excl, ex);
   upload_vec(c->dnear_ptr, c->near_ptr);
   upload_vec(c->dnear_idx, c->near_idx.empty() ? std::vector<int>{0} : c->near_idx);
+  upload_vec(c->dclose_ptr, c->close_ptr);
+  upload_vec(c->dclose_idx, c->close_idx.empty() ? std::vector<int>{0} : c->close_idx);
   upload_vec(c->otab, otab);
   upload_vec(c->otab_f, otab_f);
   upload_vec(c->osrc, osrc);

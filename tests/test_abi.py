@@ -58,7 +58,9 @@ def test_options_struct_matches_the_header():
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libbie.so not built")
 @pytest.mark.parametrize("bad", [dict(p=0), dict(p=21), dict(n_phi=7), dict(n_phi=6), dict(near_method=2),
-                                 dict(legendre_mfma=2), dict(n_spheres=0), dict(n_spheres=65537)])
+                                 dict(legendre_mfma=2), dict(n_spheres=0), dict(n_spheres=65537),
+                                 dict(near_gap=float("inf")), dict(near_gap=float("nan")),
+                                 dict(near_gap=0.0, near_tol=float("nan")), dict(near_gap=0.0, near_tol=2.0)])
 def test_invalid_options_are_rejected_before_any_device_call(bad):
     import numpy as np
     from paper_1707_06551_amd import bie
@@ -66,9 +68,9 @@ def test_invalid_options_are_rejected_before_any_device_call(bad):
     L.bie_build_spheres.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
     L.bie_build_spheres.restype = ctypes.c_int
     L.bie_last_error.restype = ctypes.c_char_p
-    kw = dict(p=4, n_phi=0, near_method=0, legendre_mfma=0, n_spheres=2)
+    kw = dict(p=4, n_phi=0, near_method=0, legendre_mfma=0, n_spheres=2, near_gap=1.0, near_tol=0.0)
     kw.update(bad)
-    o = bie.Opts(kw["p"], kw["n_phi"], 1.0, 0, None, kw["near_method"], kw["legendre_mfma"])
+    o = bie.Opts(kw["p"], kw["n_phi"], kw["near_gap"], 0, None, kw["near_method"], kw["legendre_mfma"], kw["near_tol"])
     centres = np.arange(3 * max(kw["n_spheres"], 1), dtype=np.float64) * 3.0
     h = ctypes.c_void_p()
     rc = L.bie_build_spheres(centres.ctypes.data, kw["n_spheres"], ctypes.byref(o), ctypes.byref(h))
