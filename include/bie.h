@@ -214,12 +214,34 @@ int bie_vsh_inverse(bie_ctx* ctx, int precision, const double* coef, double* u);
 
 typedef struct {
   double tol;        /* stop when ||b - A x||_2 <= tol ||b||_2 (true residual)         */
-  int restart;       /* Krylov dimension per cycle (<= 0 selects 100)                    */
+  int restart;       /* Krylov dimension per cycle (<= 0 selects 100, > 500 BIE_EINVAL) */
   int max_iter;      /* total inner iterations (<= 0 selects 1000)                      */
   int precision;     /* BIE_FP64 or BIE_MIXED                                           */
   int precond;       /* BIE_PC_NONE, _M0 or _MLP, optionally | BIE_PC_RIGID             */
   double inner_tol;  /* BIE_MIXED inner tolerance (<= 0 selects 1e-4)                   */
+  const double* x0;  /* initial guess (device float64, the solve's own unknown vector:
+                        psi (3N) for resistance, [mu; v; omega] (3N + 6 n_b) for the
+                        bordered mobility form, mu (3N) for the traction form, x of
+                        bie_solve), or NULL for x0 = 0.  The first true residual is
+                        b - A x0, so passing a converged solution back returns after
+                        that one float64 matvec with iters = 0 (a restart = resume).
+                        Read only; may alias no output                                   */
+  double* res_hist;  /* optional host buffer of res_hist_cap doubles (NULL: none): the
+                        GMRES residual estimate ||r_k|| / ||b|| after every iteration
+                        k (all cycles, refinement steps and a fallback, in order);
+                        bie_solve_info.res_hist_len reports how many were written        */
+  int res_hist_cap;
 } bie_solve_opts;
+
+/* Indices of bie_solve_info.t_stage_s: device time of each step of the hot path summed
+ * over one solve, from HIP events recorded on the context's stream around every launch
+ * of that step (only while a solve runs with info != NULL). */
+#define BIE_T_TRANSFORM 0  /* forward transform, self term, inverse (Section 2.1, Theorem 2; one fused launch) */
+#define BIE_T_NEAR      1  /* near-pair series (Section 4.1, Eqs. 3.6-3.11)                                    */
+#define BIE_T_FAR       2  /* far-field smooth quadrature (Eq. 4.4) with the completion flow (Eqs. 5.18-5.19) */
+#define BIE_T_PRECOND   3  /* preconditioner (M0 and the coarse corrections)                                  */
+#define BIE_T_KRYLOV    4  /* GMRES: orthogonalisation, updates, residual norms                                */
+#define BIE_T_OTHER     5  /* right-hand side, read-out and the local terms of the traction form              */
 
 typedef struct {
   int iters;            /* GMRES iterations (all cycles, all refinement steps)          */
@@ -229,6 +251,12 @@ typedef struct {
   int fallback_used;    /* 1 if the preconditioned solve stalled and was restarted plain */
   double rel_residual;  /* final true relative residual                                */
   double seconds;       /* wall time of the solve (device synchronised)                 */
+  double t_stage_s[8];  /* device seconds per step, indexed by BIE_T_*; 6, 7 are 0      */
+  long long pairs_evaluated; /* far-field node pairs (target node, source node on a
+                                well-separated sphere) summed over every matvec        */
+  long long near_evals;      /* near-series evaluations (target node, near source
+                                sphere) summed over every matvec                       */
+  int res_hist_len;     /* entries written to bie_solve_opts.res_hist                   */
 } bie_solve_info;
 
 /* Resistance problem (Problem 5, Eqs. 5.18-5.19): given rigid velocities v and angular

@@ -50,16 +50,25 @@ class Opts(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
-                ("precision", ctypes.c_int), ("precond", ctypes.c_int), ("inner_tol", ctypes.c_double)]
+                ("precision", ctypes.c_int), ("precond", ctypes.c_int), ("inner_tol", ctypes.c_double),
+                ("x0", ctypes.c_void_p), ("res_hist", ctypes.c_void_p), ("res_hist_cap", ctypes.c_int)]
+
+
+T_TRANSFORM, T_NEAR, T_FAR, T_PRECOND, T_KRYLOV, T_OTHER = range(6)
+STAGE_NAMES = ("transform", "near", "far", "precond", "krylov", "other")
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("outer_steps", ctypes.c_int), ("matvecs_fp64", ctypes.c_int),
                 ("matvecs_mixed", ctypes.c_int), ("fallback_used", ctypes.c_int),
-                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("t_stage_s", ctypes.c_double * 8), ("pairs_evaluated", ctypes.c_longlong),
+                ("near_evals", ctypes.c_longlong), ("res_hist_len", ctypes.c_int)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "t_stage_s"}
+        d["t_stage_s"] = {n: self.t_stage_s[i] for i, n in enumerate(STAGE_NAMES)}
+        return d
 
 
 _lib = None
@@ -257,6 +266,11 @@ class Spheres:
         d, t = ctypes.c_double(), ctypes.c_double()
         _check(L.bie_near_gap(h, ctypes.byref(d), ctypes.byref(t)))
         self.near_gap, self.near_tol = d.value, t.value
+        cnt = ctypes.c_int64()
+        _check(L.bie_near_pairs(h, ctypes.byref(cnt), None))
+        self.n_near = cnt.value
+        # node pairs of one far-field pass: all ordered pairs of distinct, well-separated spheres
+        self.far_node_pairs = (self.nb * (self.nb - 1) - self.n_near) * self.P * self.P
 
     def close(self):
         if getattr(self, "_h", None):
@@ -304,15 +318,17 @@ class Spheres:
         _check(lib().bie_vsh_inverse(self._h, precision, _dptr(coef), _dptr(u)))
         return u
 
-    def solve(self, op, b, tol=1e-8, restart=100, max_iter=1000, precision=FP64, precond=PC_NONE, inner_tol=1e-4):
+    def solve(self, op, b, tol=1e-8, restart=100, max_iter=1000, precision=FP64, precond=PC_NONE, inner_tol=1e-4,
+              x0=None, history=0):
         """Generic solve A x = b (device tensors) for OP_DN_BIE, OP_MOBILITY, OP_SD_BIE or OP_KL_BIE."""
         import torch
         x = torch.empty_like(b)
         info = SolveInfo()
-        so = self._sopts(tol, restart, max_iter, precision, precond, inner_tol)
+        hist = np.zeros(history) if history else None
+        so = self._sopts(tol, restart, max_iter, precision, precond, inner_tol, x0, hist)
         rc = lib().bie_solve(self._h, op, _dptr(b), _dptr(x), ctypes.byref(so), ctypes.byref(info))
         _check(rc, allow_noconv=True)
-        return x, dict(info.as_dict(), converged=(rc == OK))
+        return x, self._info(info, rc, hist)
 
     def apply_precond(self, op, r, precond=PC_M0, precision=FP64):
         import torch
@@ -328,7 +344,8 @@ class Spheres:
         _check(lib().bie_apply_laplace(self._h, kind, eta, _dptr(q), _dptr(out)))
         return out
 
-    def solve_magnetic(self, H0, eta, tol=1e-10, restart=100, max_iter=1000, precond=PC_M0, want_q=False):
+    def solve_magnetic(self, H0, eta, tol=1e-10, restart=100, max_iter=1000, precond=PC_M0, want_q=False, x0=None,
+                       history=0):
         """Problem 3: magnetic forces and torques (nb, 3) on the spheres in the field H0."""
         import torch
         h = np.ascontiguousarray(H0, dtype=np.float64).reshape(3)
@@ -336,11 +353,12 @@ class Spheres:
         T = np.empty((self.nb, 3))
         q = torch.empty(self.N, dtype=torch.float64, device=f"cuda:{self.device}") if want_q else None
         info = SolveInfo()
-        so = self._sopts(tol, restart, max_iter, FP64, precond, 1e-4)
+        hist = np.zeros(history) if history else None
+        so = self._sopts(tol, restart, max_iter, FP64, precond, 1e-4, x0, hist)
         rc = lib().bie_solve_magnetic(self._h, _hptr(h), eta, ctypes.byref(so), _dptr(q) if q is not None else None,
                                       _hptr(F), _hptr(T), ctypes.byref(info))
         _check(rc, allow_noconv=True)
-        return F, T, q, dict(info.as_dict(), converged=(rc == OK))
+        return F, T, q, self._info(info, rc, hist)
 
     def eval_field(self, op, mu, targets, u=None):
         """Layer potential of op (OP_S, OP_D, OP_SD_BIE, OP_DN_BIE) of the node density mu
@@ -385,11 +403,20 @@ class Spheres:
         _check(lib().bie_precond_load(self._h, _hptr(w), w.size))
 
     @staticmethod
-    def _sopts(tol, restart, max_iter, precision, precond, inner_tol):
-        return SolveOpts(tol, restart, max_iter, precision, precond, inner_tol)
+    def _sopts(tol, restart, max_iter, precision, precond, inner_tol, x0=None, hist=None):
+        return SolveOpts(tol, restart, max_iter, precision, precond, inner_tol,
+                         _dptr(x0) if x0 is not None else None, _hptr(hist) if hist is not None else None,
+                         0 if hist is None else hist.size)
+
+    @staticmethod
+    def _info(info, rc, hist):
+        d = dict(info.as_dict(), converged=(rc == OK))
+        if hist is not None:
+            d["res_hist"] = hist[:info.res_hist_len].copy()
+        return d
 
     def solve_resistance(self, v, omega, tol=1e-8, restart=100, max_iter=1000, precision=FP64, precond=PC_NONE,
-                         inner_tol=1e-4, want_psi=False):
+                         inner_tol=1e-4, want_psi=False, x0=None, history=0):
         import torch
         v = np.ascontiguousarray(v, dtype=np.float64)
         om = np.ascontiguousarray(omega, dtype=np.float64)
@@ -397,14 +424,15 @@ class Spheres:
         T = np.empty((self.nb, 3))
         psi = torch.empty(3 * self.N, dtype=torch.float64, device=f"cuda:{self.device}") if want_psi else None
         info = SolveInfo()
-        so = self._sopts(tol, restart, max_iter, precision, precond, inner_tol)
+        hist = np.zeros(history) if history else None
+        so = self._sopts(tol, restart, max_iter, precision, precond, inner_tol, x0, hist)
         rc = lib().bie_solve_resistance(self._h, _hptr(v), _hptr(om), ctypes.byref(so), _hptr(F), _hptr(T),
                                         _dptr(psi) if psi is not None else None, ctypes.byref(info))
         _check(rc, allow_noconv=True)
-        return F, T, psi, dict(info.as_dict(), converged=(rc == OK))
+        return F, T, psi, self._info(info, rc, hist)
 
     def solve_mobility_traction(self, F, T, tol=1e-8, restart=100, max_iter=1000, precision=FP64,
-                                precond=PC_M0, inner_tol=1e-4, want_mu=False):
+                                precond=PC_M0, inner_tol=1e-4, want_mu=False, x0=None, history=0):
         """Problem 2 in the paper's form (Eqs. 5.7-5.8): (v, omega, mu or None, info)."""
         import torch
         F = np.ascontiguousarray(F, dtype=np.float64)
@@ -413,14 +441,15 @@ class Spheres:
         om = np.empty((self.nb, 3))
         mu = torch.empty(3 * self.N, dtype=torch.float64, device=f"cuda:{self.device}") if want_mu else None
         info = SolveInfo()
-        so = self._sopts(tol, restart, max_iter, precision, precond, inner_tol)
+        hist = np.zeros(history) if history else None
+        so = self._sopts(tol, restart, max_iter, precision, precond, inner_tol, x0, hist)
         rc = lib().bie_solve_mobility_traction(self._h, _hptr(F), _hptr(T), ctypes.byref(so), _hptr(v), _hptr(om),
                                                _dptr(mu) if mu is not None else None, ctypes.byref(info))
         _check(rc, allow_noconv=True)
-        return v, om, mu, dict(info.as_dict(), converged=(rc == OK))
+        return v, om, mu, self._info(info, rc, hist)
 
     def solve_mobility(self, F, T, slip=None, tol=1e-8, restart=100, max_iter=1000, precision=FP64,
-                       precond=PC_NONE, inner_tol=1e-4, want_mu=False):
+                       precond=PC_NONE, inner_tol=1e-4, want_mu=False, x0=None, history=0):
         import torch
         F = np.ascontiguousarray(F, dtype=np.float64)
         T = np.ascontiguousarray(T, dtype=np.float64)
@@ -428,9 +457,10 @@ class Spheres:
         om = np.empty((self.nb, 3))
         mu = torch.empty(3 * self.N, dtype=torch.float64, device=f"cuda:{self.device}") if want_mu else None
         info = SolveInfo()
-        so = self._sopts(tol, restart, max_iter, precision, precond, inner_tol)
+        hist = np.zeros(history) if history else None
+        so = self._sopts(tol, restart, max_iter, precision, precond, inner_tol, x0, hist)
         rc = lib().bie_solve_mobility(self._h, _hptr(F), _hptr(T), _dptr(slip) if slip is not None else None,
                                       ctypes.byref(so), _hptr(v), _hptr(om),
                                       _dptr(mu) if mu is not None else None, ctypes.byref(info))
         _check(rc, allow_noconv=True)
-        return v, om, mu, dict(info.as_dict(), converged=(rc == OK))
+        return v, om, mu, self._info(info, rc, hist)

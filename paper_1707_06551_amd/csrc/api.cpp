@@ -70,17 +70,28 @@ void apply(bie_ctx* c, int op, int precision, const double* mu, double* u) {
   } else {
     self_lambda(spec, c->p, v.lam);
   }
-  launch_vsh(c, precision, v);
+  {
+    StageScope ts(c, BIE_T_TRANSFORM);
+    launch_vsh(c, precision, v);
+  }
   // L of Eq. 5.8 on the own sphere: int mu + (int (y - c) x mu) x (x - c)
-  if (spec.rigid_local && (stages & BIE_STAGE_SELF))
+  if (spec.rigid_local && (stages & BIE_STAGE_SELF)) {
+    StageScope ts(c, BIE_T_OTHER);
     add_rigid_local(c, c->moments.as<double>(), u, c->poly ? c->radius_d.as<double>() : nullptr);
+  }
   if (stages & BIE_STAGE_NEAR) {
+    StageScope ts(c, BIE_T_NEAR);
     if (spec.traction)
       launch_near_traction(c, u);
     else
       launch_near(c, spec, u);
+    if (c->timer.on) c->timer.near_evals += (long long)c->near_idx.size() * c->P;
   }
-  if (stages & BIE_STAGE_FAR) launch_far(c, precision, spec, u);
+  if (stages & BIE_STAGE_FAR) {
+    StageScope ts(c, BIE_T_FAR);
+    launch_far(c, precision, spec, u);
+    if (c->timer.on) c->timer.far_pairs += c->far_node_pairs;
+  }
 }
 
 // Block-diagonal preconditioner M0: the exact inverse of every sphere's isolated self
@@ -310,6 +321,7 @@ void bie_free(bie_ctx* c) {
                          &c->rec, &c->coef, &c->q, &c->partial, &c->moments, &c->scal, &c->krylov, &c->zbasis,
                          &c->vec[0], &c->vec[1], &c->vec[2], &c->vec[3], &c->vec[4], &c->vec[5]};
   for (auto* b : bufs) b->release();
+  bie::timer_release(c);
   delete c;
 }
 

@@ -50,6 +50,19 @@ struct OpSpec {
 };
 OpSpec op_spec(int op_base);
 
+// Device time per step of the hot path during one solve (bie_solve_info.t_stage_s):
+// pairs of HIP events recorded on the context's stream around the launches of a step,
+// drawn from a pool that the context keeps; nested scopes record only the outermost.
+struct StageTimer {
+  bool on = false;
+  int depth = 0;
+  std::vector<hipEvent_t> ev;  // 2 per record
+  std::vector<int> tag;        // step of each record
+  size_t used = 0;
+  long long far_pairs = 0;     // far-field node pairs of the solve's matvecs
+  long long near_evals = 0;    // near-series evaluations of the solve's matvecs
+};
+
 }  // namespace bie
 
 struct bie_ctx {
@@ -60,6 +73,8 @@ struct bie_ctx {
   double near_tol = 0.0;   // precision d* was calibrated for (0 when near_gap was given)
   int device = 0;
   hipStream_t stream = nullptr;
+  int64_t far_node_pairs = 0;  // node pairs on distinct, well-separated spheres (one far pass)
+  bie::StageTimer timer;
 
   // host copies
   std::vector<double> centres;  // nb x 3
@@ -79,6 +94,10 @@ struct bie_ctx {
   bie::DevBuf excl;       // nb x nwords uint32: bit s of row t set if s == t or (t, s) near
   int nwords = 0;
   bie::DevBuf dnear_ptr, dnear_idx;
+  bie::DevBuf dnear_order;     // target spheres with near neighbours, longest near list first
+  int64_t n_near_targets = 0;
+  bie::DevBuf neartab;         // nb x near_slots x 16 double: per-source series constants (near.hip)
+  int near_slots = 0;
   bie::DevBuf dclose_ptr, dclose_idx;
   bie::DevBuf otab, otab_f;    // P x 4 unit offsets of the nodes of a sphere (double / float)
   bie::DevBuf osrc, osrc_f;    // P x 4 the same offsets times -2 (far-field source table)
@@ -166,8 +185,28 @@ void require_unit(const bie_ctx* c, const char* what);
 void launch_near(bie_ctx* c, const OpSpec& spec, double* u);
 void launch_near_rot(bie_ctx* c, const OpSpec& spec, double* u);
 void series_radial(double a_s, double a_d, int p, double* kvv, double* kww, double* kwv, double* kxx);
+int near_table_slots(int p, int mmax);
+std::vector<int> near_launch_order(const std::vector<int>& near_ptr, int64_t nb);
 void launch_far(bie_ctx* c, int precision, const OpSpec& spec, double* u);
 void apply(bie_ctx* c, int op, int precision, const double* mu, double* u);
+
+// Records the device time of the enclosed launches under step `stage` (BIE_T_*) while
+// c->timer.on; no-op otherwise.
+class StageScope {
+ public:
+  StageScope(bie_ctx* c, int stage);
+  ~StageScope();
+  StageScope(const StageScope&) = delete;
+  StageScope& operator=(const StageScope&) = delete;
+
+ private:
+  bie_ctx* c_;
+  bool rec_ = false;
+};
+void timer_start(bie_ctx* c);
+// Waits for the recorded events and sums their durations per step into t[8]; stops the timer.
+void timer_collect(bie_ctx* c, double t[8]);
+void timer_release(bie_ctx* c);
 
 // Set-up helpers (setup.cpp): Gauss-Legendre rule (nodes descending), Legendre tables
 // at one latitude per coefficient slot (Pbar, dPbar/dtheta, m Pbar / sin theta), the

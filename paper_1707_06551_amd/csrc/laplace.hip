@@ -173,35 +173,38 @@ __global__ __launch_bounds__(1024) void lap_near_kernel(NearLapParams a) {
   double* cs = sm;
   double* rec = sm + 2 * nc;
   for (int i = threadIdx.x; i < 6 * nc; i += blockDim.x) rec[i] = a.rec[i];
-  const int g = threadIdx.x;
-  const bool active = g < a.P;
-  double ox = 0, oy = 0, oz = 0;
-  if (active) {
-    ox = a.otab[4 * g];
-    oy = a.otab[4 * g + 1];
-    oz = a.otab[4 * g + 2];
-  }
   const double ctx = a.centres4[4 * t], cty = a.centres4[4 * t + 1], ctz = a.centres4[4 * t + 2];
   const double at = a.radius ? a.radius[t] : 1.0;
-  double v = 0, gx = 0, gy = 0, gz = 0;
-  for (int e = s0; e < s1; ++e) {
-    const int s = a.near_idx[e];
-    __syncthreads();
-    for (int i = threadIdx.x; i < 2 * nc; i += blockDim.x) cs[i] = a.coef[(size_t)s * 2 * nc + i];
-    __syncthreads();
+  // the target nodes in chunks of the block size (grids with more than 1024 nodes)
+  for (int g0 = 0; g0 < a.P; g0 += blockDim.x) {
+    const int g = g0 + threadIdx.x;
+    const bool active = g < a.P;
+    double ox = 0, oy = 0, oz = 0;
+    if (active) {
+      ox = a.otab[4 * g];
+      oy = a.otab[4 * g + 1];
+      oz = a.otab[4 * g + 2];
+    }
+    double v = 0, gx = 0, gy = 0, gz = 0;
+    for (int e = s0; e < s1; ++e) {
+      const int s = a.near_idx[e];
+      __syncthreads();
+      for (int i = threadIdx.x; i < 2 * nc; i += blockDim.x) cs[i] = a.coef[(size_t)s * 2 * nc + i];
+      __syncthreads();
+      if (!active) continue;
+      const double ias = a.radius ? 1.0 / a.radius[s] : 1.0;
+      laplace_series(a.p, a.mmax, cs, rec, ((ctx - a.centres4[4 * s]) + at * ox) * ias,
+                     ((cty - a.centres4[4 * s + 1]) + at * oy) * ias, ((ctz - a.centres4[4 * s + 2]) + at * oz) * ias,
+                     v, gx, gy, gz);
+    }
     if (!active) continue;
-    const double ias = a.radius ? 1.0 / a.radius[s] : 1.0;
-    laplace_series(a.p, a.mmax, cs, rec, ((ctx - a.centres4[4 * s]) + at * ox) * ias,
-                   ((cty - a.centres4[4 * s + 1]) + at * oy) * ias, ((ctz - a.centres4[4 * s + 2]) + at * oz) * ias, v,
-                   gx, gy, gz);
-  }
-  if (!active) return;
-  const int64_t node = (int64_t)t * a.P + g;
-  if (a.out) a.out[node] += a.scale * (gx * ox + gy * oy + gz * oz);
-  if (a.grad) {
-    a.grad[3 * node] += gx;
-    a.grad[3 * node + 1] += gy;
-    a.grad[3 * node + 2] += gz;
+    const int64_t node = (int64_t)t * a.P + g;
+    if (a.out) a.out[node] += a.scale * (gx * ox + gy * oy + gz * oz);
+    if (a.grad) {
+      a.grad[3 * node] += gx;
+      a.grad[3 * node + 1] += gy;
+      a.grad[3 * node + 2] += gz;
+    }
   }
 }
 

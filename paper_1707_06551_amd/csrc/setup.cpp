@@ -261,7 +261,6 @@ void build(bie_ctx* c, const double* centres, const double* radii, int64_t nb, c
   c->legendre_mfma = o->legendre_mfma;
   c->device = o->device;
   c->stream = (hipStream_t)o->hip_stream;
-  BIE_HIP(hipSetDevice(c->device));
   c->centres.assign(centres, centres + 3 * nb);
   for (double x : c->centres)
     if (!std::isfinite(x)) throw Error{BIE_EINVAL, "non-finite centre coordinate"};
@@ -347,6 +346,7 @@ void build(bie_ctx* c, const double* centres, const double* radii, int64_t nb, c
     c->close_idx.insert(c->close_idx.end(), cls[k].begin(), cls[k].end());
     c->close_ptr[k + 1] = (int)c->close_idx.size();
   }
+  c->far_node_pairs = (nb * (nb - 1) - total) * (int64_t)c->P * c->P;
   c->nwords = (int)((nb + 31) / 32);
   std::vector<uint32_t> ex((size_t)nb * c->nwords, 0u);
   for (int64_t k = 0; k < nb; ++k) {
@@ -432,7 +432,8 @@ void build(bie_ctx* c, const double* centres, const double* radii, int64_t nb, c
   std::vector<double> rec = recurrence_table(c->p, c->mmax);
   auto tof = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
 
-  // ---- device upload -------------------------------------------------------------
+  // ---- device upload (every input has been checked and every host table built) -------
+  BIE_HIP(hipSetDevice(c->device));
   std::vector<double> c4(4 * nb);
   for (int64_t k = 0; k < nb; ++k) {
     for (int d = 0; d < 3; ++d) c4[4 * k + d] = centres[3 * k + d];
@@ -470,6 +471,15 @@ void build(bie_ctx* c, const double* centres, const double* radii, int64_t nb, c
   c->nsplit = std::max(1, std::min(ns, 64));
   c->partial.alloc((size_t)c->nsplit * c->N * 3 * sizeof(double));
   upload_vec(c->tlat_d, tt);
+  if (!c->near_idx.empty()) {
+    const std::vector<int> order = near_launch_order(c->near_ptr, nb);
+    c->n_near_targets = (int64_t)order.size();
+    upload_vec(c->dnear_order, order);
+    if (c->near_method == 0) {
+      c->near_slots = near_table_slots(c->p, c->mmax);
+      c->neartab.alloc((size_t)nb * c->near_slots * 16 * sizeof(double));
+    }
+  }
   if (c->near_method == 1) {
     upload_vec(c->wig, wigner_x90(c->p));
     c->nearcoef.alloc((size_t)nb * 3 * nc * 2 * sizeof(double));

@@ -122,6 +122,60 @@ double dev_norm(bie_ctx* c, const double* x, int64_t n) {
   return std::sqrt(h);
 }
 
+StageScope::StageScope(bie_ctx* c, int stage) : c_(c) {
+  StageTimer& t = c->timer;
+  if (!t.on || t.depth++ > 0) return;
+  if (2 * (t.used + 1) > t.ev.size()) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+      if (e0) (void)hipEventDestroy(e0);
+      return;
+    }
+    t.ev.push_back(e0);
+    t.ev.push_back(e1);
+  }
+  if (t.tag.size() <= t.used) t.tag.resize(t.used + 1);
+  t.tag[t.used] = stage;
+  rec_ = hipEventRecord(t.ev[2 * t.used], c->stream) == hipSuccess;
+}
+
+StageScope::~StageScope() {
+  StageTimer& t = c_->timer;
+  if (t.depth > 0) --t.depth;
+  if (!rec_) return;
+  if (hipEventRecord(t.ev[2 * t.used + 1], c_->stream) == hipSuccess) ++t.used;
+}
+
+void timer_start(bie_ctx* c) {
+  c->timer.on = true;
+  c->timer.depth = 0;
+  c->timer.used = 0;
+  c->timer.far_pairs = 0;
+  c->timer.near_evals = 0;
+}
+
+void timer_collect(bie_ctx* c, double t[8]) {
+  StageTimer& tm = c->timer;
+  for (int i = 0; i < 8; ++i) t[i] = 0.0;
+  tm.on = false;
+  if (tm.used == 0) return;
+  BIE_HIP(hipEventSynchronize(tm.ev[2 * tm.used - 1]));
+  for (size_t i = 0; i < tm.used; ++i) {
+    float ms = 0.0f;
+    BIE_HIP(hipEventElapsedTime(&ms, tm.ev[2 * i], tm.ev[2 * i + 1]));
+    t[tm.tag[i] & 7] += 1e-3 * ms;
+  }
+  tm.used = 0;
+}
+
+void timer_release(bie_ctx* c) {
+  for (hipEvent_t e : c->timer.ev) (void)hipEventDestroy(e);
+  c->timer.ev.clear();
+  c->timer.tag.clear();
+  c->timer.used = 0;
+  c->timer.on = false;
+}
+
 namespace {
 
 struct Krylov {
@@ -155,18 +209,22 @@ void apply_A(const OpCtx& o, const double* x, double* y) {
 
 void apply_M(const OpCtx& o, const double* x, double* z, int64_t n) {
   (void)n;
+  StageScope ts(o.c, BIE_T_PRECOND);
   apply_precond(o.c, o.op, o.precision, o.precond, x, z);
 }
 
 // One flexible GMRES solve of A d = r from d = 0 to relative tolerance tol (estimate);
 // returns iterations used, writes d.  best-effort on stagnation (max_it reached).
 int fgmres(const OpCtx& o, Krylov& K, const double* r, double rnorm, double tol, int max_it, double* d,
-           std::vector<double>* hist, bool* bad) {
+           std::vector<double>* hist, double hist_den, bool* bad) {
   bie_ctx* c = o.c;
   const int64_t n = K.n;
   const int m = K.m;
   *bad = false;
-  dev_fill(c, d, 0.0, n);
+  {
+    StageScope ts(c, BIE_T_KRYLOV);
+    dev_fill(c, d, 0.0, n);
+  }
   if (rnorm == 0.0) return 0;
   int it = 0;
   double cur = rnorm;
@@ -175,9 +233,11 @@ int fgmres(const OpCtx& o, Krylov& K, const double* r, double rnorm, double tol,
   while (it < max_it) {
     // V_0 = current residual / its norm.  First cycle: r; later cycles: r - A d.
     if (rr == r) {
+      StageScope ts(c, BIE_T_KRYLOV);
       dev_axpby(c, 1.0 / cur, r, 0.0, K.V, n);
     } else {
-      apply_A(o, d, K.w);  // A M? d is already in solution space (d = Z y), so plain A
+      apply_A(o, d, K.w);  // d is already in solution space (d = Z y), so plain A
+      StageScope ts(c, BIE_T_KRYLOV);
       dev_axpby(c, 1.0, r, -1.0, K.w, n);
       cur = dev_norm(c, K.w, n);
       if (cur <= tol * rnorm) break;
@@ -193,6 +253,7 @@ int fgmres(const OpCtx& o, Krylov& K, const double* r, double rnorm, double tol,
       double* zj = K.flexible ? K.Z + (int64_t)j * n : vj;
       if (K.flexible) apply_M(o, vj, zj, n);
       apply_A(o, zj, K.w);
+      StageScope ts(c, BIE_T_KRYLOV);
       // CGS2
       dots_dev(c, K.V, n, j + 1, K.w, n, K.hdev);
       k_gemv<<<grid_for(n), 256, 0, c->stream>>>(K.V, n, j + 1, K.hdev, -1.0, K.w, n);
@@ -234,7 +295,7 @@ int fgmres(const OpCtx& o, Krylov& K, const double* r, double rnorm, double tol,
           return it;
         }
       }
-      if (hist) hist->push_back(est / rnorm);
+      if (hist) hist->push_back(est / hist_den);
       if (est <= tol * rnorm || den == 0.0) {
         ++j;
         done = true;
@@ -249,6 +310,7 @@ int fgmres(const OpCtx& o, Krylov& K, const double* r, double rnorm, double tol,
       for (int l = i + 1; l < kk; ++l) s -= H[(size_t)l * (m + 1) + i] * y[l];
       y[i] = s / H[(size_t)i * (m + 1) + i];
     }
+    StageScope ts(c, BIE_T_KRYLOV);
     double* ydev = K.hdev + 2 * (m + 1) + 8;
     BIE_HIP(hipMemcpyAsync(ydev, y.data(), kk * sizeof(double), hipMemcpyHostToDevice, c->stream));
     k_gemv<<<grid_for(n), 256, 0, c->stream>>>(K.flexible ? K.Z : K.V, n, kk, ydev, +1.0, d, n);
@@ -272,6 +334,7 @@ int solve(bie_ctx* c, int op, const double* b, double* x, int64_t n, const bie_s
   if (o.max_iter <= 0) o.max_iter = 1000;
   if (!(o.inner_tol > 0)) o.inner_tol = 1e-4;
   if (o.restart > 500) throw Error{BIE_EINVAL, "restart must be <= 500"};
+  if (o.res_hist && o.res_hist_cap < 0) throw Error{BIE_EINVAL, "res_hist_cap must be >= 0"};
   const int pc_base = o.precond & ~BIE_PC_RIGID;
   if (pc_base == BIE_PC_MLP && !c->theta_ready) throw Error{BIE_EINVAL, "BIE_PC_MLP needs bie_precond_load first"};
   if (pc_base < BIE_PC_NONE || pc_base > BIE_PC_MLP) throw Error{BIE_EINVAL, "unknown preconditioner"};
@@ -294,25 +357,44 @@ int solve(bie_ctx* c, int op, const double* b, double* x, int64_t n, const bie_s
   double* r = c->vec[1].as<double>();
   double* d = c->vec[2].as<double>();
   int mv64 = 0, mv32 = 0;
-  const double bnorm = dev_norm(c, b, n);
-  dev_fill(c, x, 0.0, n);
+  if (info) timer_start(c);
+  std::vector<double> hist;
+  std::vector<double>* hp = (o.res_hist && o.res_hist_cap > 0) ? &hist : nullptr;
+  double bnorm;
+  {
+    StageScope ts(c, BIE_T_KRYLOV);
+    bnorm = dev_norm(c, b, n);
+    if (o.x0) {
+      if (o.x0 != x) dev_copy(c, o.x0, x, n);
+    } else {
+      dev_fill(c, x, 0.0, n);
+    }
+  }
   int iters = 0, outer = 0, fallback = 0;
+  bool fallback_failed = false;
   double rel = 0.0;
   int status = BIE_ENOCONV;
   if (bnorm == 0.0) {
+    // b = 0: the solution is 0 whatever the initial guess
+    if (o.x0) {
+      StageScope ts(c, BIE_T_KRYLOV);
+      dev_fill(c, x, 0.0, n);
+    }
     status = BIE_OK;
   } else {
     OpCtx op64{c, op, BIE_FP64, o.precond, &mv64, &mv32};
     OpCtx opin{c, op, o.precision, o.precond, &mv64, &mv32};
-    bool first = true;
+    bool first = o.x0 == nullptr;
     while (iters < o.max_iter) {
       // r = b - A x (float64)
       double rn;
       if (first) {
+        StageScope ts(c, BIE_T_KRYLOV);
         dev_copy(c, b, r, n);
         rn = bnorm;
       } else {
         apply_A(op64, x, r);
+        StageScope ts(c, BIE_T_KRYLOV);
         dev_axpby(c, 1.0, b, -1.0, r, n);
         rn = dev_norm(c, r, n);
       }
@@ -327,9 +409,12 @@ int solve(bie_ctx* c, int op, const double* b, double* x, int64_t n, const bie_s
       // inner tolerance: refinement asks for inner_tol, a float64 solve for the target
       double itol = (o.precision == BIE_MIXED) ? std::max(o.inner_tol, 0.5 * o.tol / rel) : 0.7 * o.tol / rel;
       bool bad = false;
-      iters += fgmres(fallback ? op64 : opin, K, r, rn, itol, o.max_iter - iters, d, nullptr, &bad);
+      iters += fgmres(fallback ? op64 : opin, K, r, rn, itol, o.max_iter - iters, d, hp, bnorm, &bad);
       if (bad) {
-        if (fallback) break;
+        if (fallback) {
+          fallback_failed = true;
+          break;
+        }
         // stagnation / non-finite values: restart plain float64 GMRES from x
         fallback = 1;
         opin.precond = BIE_PC_NONE;
@@ -337,8 +422,18 @@ int solve(bie_ctx* c, int op, const double* b, double* x, int64_t n, const bie_s
         K.flexible = false;
         continue;
       }
-      dev_axpby(c, 1.0, d, 1.0, x, n);
+      {
+        StageScope ts(c, BIE_T_KRYLOV);
+        dev_axpby(c, 1.0, d, 1.0, x, n);
+      }
       if (o.precision != BIE_MIXED && outer > 50) break;
+    }
+    if (status != BIE_OK && iters > 0 && !fallback_failed) {
+      // not converged: report the true residual of the returned iterate
+      apply_A(op64, x, r);
+      StageScope ts(c, BIE_T_KRYLOV);
+      dev_axpby(c, 1.0, b, -1.0, r, n);
+      rel = dev_norm(c, r, n) / bnorm;
     }
   }
   BIE_HIP(hipStreamSynchronize(c->stream));
@@ -350,6 +445,15 @@ int solve(bie_ctx* c, int op, const double* b, double* x, int64_t n, const bie_s
     info->fallback_used = fallback;
     info->rel_residual = rel;
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    timer_collect(c, info->t_stage_s);
+    info->pairs_evaluated = c->timer.far_pairs;
+    info->near_evals = c->timer.near_evals;
+    info->res_hist_len = 0;
+  }
+  if (hp) {
+    const int k = (int)std::min<size_t>(hist.size(), (size_t)o.res_hist_cap);
+    std::memcpy(o.res_hist, hist.data(), k * sizeof(double));
+    if (info) info->res_hist_len = k;
   }
   return status;
 }

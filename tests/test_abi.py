@@ -46,14 +46,36 @@ def test_null_arguments_are_rejected_without_a_device():
     assert L.bie_build_spheres(None, 0, None, None) == -1
 
 
-def test_options_struct_matches_the_header():
-    # field order and types of bie_opts in include/bie.h against the binding's mirror
-    from paper_1707_06551_amd import bie
-    body = re.search(r"typedef struct \{(.*?)\} bie_opts;", open(HEADER).read(), re.S).group(1)
+def header_struct(name):
+    """(field, ctypes type) of a typedef struct of include/bie.h, in order."""
+    body = re.search(r"typedef struct \{([^{}]*?)\} " + name + ";", open(HEADER).read(), re.S).group(1)
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
-    fields = re.findall(r"\b(int|double|void\*)\s+(\w+);", body)
-    ctype = {"int": ctypes.c_int, "double": ctypes.c_double, "void*": ctypes.c_void_p}
-    assert [(n, ctype[t]) for t, n in fields] == list(bie.Opts._fields_)
+    ctype = {"int": ctypes.c_int, "double": ctypes.c_double, "void*": ctypes.c_void_p, "long long": ctypes.c_longlong,
+             "const double*": ctypes.c_void_p, "double*": ctypes.c_void_p}
+    out = []
+    for t, n, k in re.findall(r"((?:const\s+)?(?:long long|int|double|void)\s*\*?)\s*(\w+)(?:\[(\d+)\])?;", body):
+        ct = ctype[re.sub(r"\s+\*", "*", t.strip())]
+        out.append((n, ct * int(k) if k else ct))
+    return out
+
+
+@pytest.mark.parametrize("name,cls", [("bie_opts", "Opts"), ("bie_solve_opts", "SolveOpts"),
+                                      ("bie_solve_info", "SolveInfo")])
+def test_structs_match_the_header(name, cls):
+    # field order, types and the resulting size of each option / result struct of
+    # include/bie.h against the binding's mirror
+    from paper_1707_06551_amd import bie
+    fields = header_struct(name)
+    mirror = getattr(bie, cls)
+    assert [n for n, _ in fields] == [n for n, _ in mirror._fields_]
+    for (n, t), (_, u) in zip(fields, mirror._fields_):
+        assert ctypes.sizeof(t) == ctypes.sizeof(u) and getattr(t, "_length_", 0) == getattr(u, "_length_", 0), n
+
+    class Ref(ctypes.Structure):
+        _fields_ = fields
+    assert ctypes.sizeof(Ref) == ctypes.sizeof(mirror)
+    for n, _ in fields:
+        assert getattr(Ref, n).offset == getattr(mirror, n).offset, n
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libbie.so not built")

@@ -5,7 +5,7 @@ import pytest
 
 from oracle.grid import Geometry
 from oracle.operators import Operators
-from tests.gpu_common import rel_err
+from tests.gpu_common import assert_close
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -53,7 +53,7 @@ def test_near_touching_pair_matches_oracle():
     out = host(s.apply(bie.OP_SD_BIE, dev(mu))).reshape(g.N, 3)
     ref = ops.apply("SD_BIE", mu)
     assert np.isfinite(out).all()
-    assert rel_err(out, ref) < 1e-11, rel_err(out, ref)
+    assert_close(out, ref, 1e-11)
     s.close()
 
 

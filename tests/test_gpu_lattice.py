@@ -8,7 +8,7 @@ import pytest
 from oracle.grid import Geometry
 from oracle.operators import Operators
 from paper_1707_06551_amd.inputs import lattice_centres
-from tests.gpu_common import max_rel, rel_err
+from tests.gpu_common import assert_close
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -41,7 +41,7 @@ def test_lattice_operator_parity(q, opname, precision):
     out = host(s.apply(OPS[opname], dev(x), precision=precision)).reshape(g.N, 3)
     ref = ops.apply(opname, x)
     tol = 1e-11 if precision == 0 else 1e-6
-    assert rel_err(out, ref) < tol, (rel_err(out, ref), max_rel(out, ref))
+    assert_close(out, ref, tol)
     s.close()
 
 
@@ -59,5 +59,5 @@ def test_largest_dense_lattice_sampled(precision):
     tg = np.concatenate([np.arange(centre * g.P, (centre + 1) * g.P), rng.choice(g.N, 48, replace=False)])
     ref = ops.apply("D", x, targets=tg)
     tol = 1e-11 if precision == 0 else 1e-6
-    assert rel_err(out[tg], ref) < tol, (rel_err(out[tg], ref), max_rel(out[tg], ref))
+    assert_close(out[tg], ref, tol)
     s.close()

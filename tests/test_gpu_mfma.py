@@ -8,7 +8,7 @@ import pytest
 
 from oracle.grid import Geometry
 from oracle.operators import Operators
-from tests.gpu_common import make_workload, max_rel, oracle_coef_to_gpu, rel_err, small_cluster
+from tests.gpu_common import assert_close, make_workload, oracle_coef_to_gpu, small_cluster
 
 pytestmark = pytest.mark.gpu
 
@@ -61,9 +61,9 @@ def test_forward_transform_on_matrix_cores(name, precision, tol):
     mu = np.random.default_rng(41).standard_normal((g.N, 3))
     coef = host(s1.vsh_forward(dev(mu), precision=precision)).reshape(g.nb, 3, s1.ncoef, 2)
     ref = oracle_coef_to_gpu(ops, [ops.coefficients(mu[..., None], k)[..., 0] for k in range(g.nb)], g.nb)
-    assert max_rel(coef, ref) < tol, max_rel(coef, ref)
+    assert_close(coef, ref, tol)
     fma = host(s0.vsh_forward(dev(mu), precision=precision)).reshape(coef.shape)
-    assert max_rel(coef, fma) < (1e-13 if precision == 0 else 1e-6)
+    assert_close(coef, fma, (1e-13 if precision == 0 else 1e-6))
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -75,7 +75,7 @@ def test_inverse_transform_on_matrix_cores(name, precision, tol):
     field = np.concatenate([ops.vsh.inverse(c) for c in coefs])
     cg = oracle_coef_to_gpu(ops, coefs, g.nb)
     out = host(s1.vsh_inverse(dev(cg), precision=precision)).reshape(g.N, 3)
-    assert max_rel(out, field) < tol, max_rel(out, field)
+    assert_close(out, field, tol)
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -90,11 +90,11 @@ def test_operators_equal_the_fma_path(name, opname, precision):
     x = dev(rng.standard_normal(n))
     a = host(s1.apply(op, x, precision=precision))
     b = host(s0.apply(op, x, precision=precision))
-    assert rel_err(a, b) < (1e-13 if precision == 0 else 1e-6), rel_err(a, b)
+    assert_close(a, b, (1e-13 if precision == 0 else 1e-6))
     if opname in ("DN_BIE", "MOBILITY"):
         za = host(s1.apply_precond(op, x, precision=precision, precond=B.PC_M0))
         zb = host(s0.apply_precond(op, x, precision=precision, precond=B.PC_M0))
-        assert rel_err(za, zb) < (1e-13 if precision == 0 else 1e-6), rel_err(za, zb)
+        assert_close(za, zb, (1e-13 if precision == 0 else 1e-6))
 
 
 def test_mobility_solve_on_matrix_cores():
@@ -110,7 +110,8 @@ def test_mobility_solve_on_matrix_cores():
         assert info["converged"]
         out.append((v, om, info["iters"]))
         s.close()
-    assert rel_err(out[0][0], out[1][0]) < 1e-9 and rel_err(out[0][1], out[1][1]) < 1e-9
+    assert_close(out[0][0], out[1][0], 1e-9)
+    assert_close(out[0][1], out[1][1], 1e-9)
     assert abs(out[0][2] - out[1][2]) <= 1
 
 

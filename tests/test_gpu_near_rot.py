@@ -10,7 +10,7 @@ import pytest
 from oracle import rotation_near as rn
 from oracle.grid import Geometry
 from oracle.operators import OPS as ORACLE_OPS, Operators
-from tests.gpu_common import max_rel, poly_cluster, rel_err, small_cluster
+from tests.gpu_common import assert_close, poly_cluster, rel_err, small_cluster
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -52,7 +52,7 @@ def test_near_stage_matches_oracle(opname):
     out = host(s.apply(OPS[opname] | bie.STAGE_NEAR, dev(mu))).reshape(g.N, 3)
     # the stage call also zero-fills u before the near part is added
     ref = rn.near_part(g, mu, a_s, a_d)
-    assert rel_err(out, ref) < 1e-11, (rel_err(out, ref), max_rel(out, ref))
+    assert_close(out, ref, 1e-11)
 
 
 @pytest.mark.parametrize("opname", ["SD_BIE", "DN_BIE"])
@@ -66,7 +66,7 @@ def test_full_operator_matches_oracle(opname, precision):
     if compl:
         ref = ref + ops.completion_part(mu)
     tol = 1e-11 if precision == 0 else 1e-6
-    assert rel_err(out, ref) < tol, (rel_err(out, ref), max_rel(out, ref))
+    assert_close(out, ref, tol)
 
 
 def test_solve_stays_within_the_projection_error():
@@ -99,7 +99,7 @@ def test_near_stage_with_wider_azimuthal_grid():
     mu = np.random.default_rng(9).standard_normal((g.N, 3))
     out = host(s.apply(OPS["SD_BIE"] | bie.STAGE_NEAR, dev(mu))).reshape(g.N, 3)
     ref = rn.near_part(g, mu, 1.0, 1.0)
-    assert rel_err(out, ref) < 1e-11, (rel_err(out, ref), max_rel(out, ref))
+    assert_close(out, ref, 1e-11)
     s.close()
 
 
@@ -128,7 +128,7 @@ def test_near_stage_with_radii_matches_oracle(opname):
     mu = np.random.default_rng(9).standard_normal((g.N, 3))
     out = host(s.apply(OPS[opname] | bie.STAGE_NEAR, dev(mu))).reshape(g.N, 3)
     ref = rn.near_part(g, mu, a_s, a_d)
-    assert rel_err(out, ref) < 1e-11, (rel_err(out, ref), max_rel(out, ref))
+    assert_close(out, ref, 1e-11)
 
 
 @pytest.mark.parametrize("opname", ["SD_BIE", "DN_BIE"])
@@ -142,7 +142,7 @@ def test_full_operator_with_radii_matches_oracle(opname, precision):
     if compl:
         ref = ref + ops.completion_part(mu)
     tol = 1e-11 if precision == 0 else 1e-6
-    assert rel_err(out, ref) < tol, (rel_err(out, ref), max_rel(out, ref))
+    assert_close(out, ref, tol)
 
 
 def test_polydisperse_solve_with_rotation():

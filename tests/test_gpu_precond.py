@@ -10,7 +10,7 @@ import pytest
 from oracle import coarse, mlp
 from oracle.grid import Geometry
 from oracle.precond import m0_resistance
-from tests.gpu_common import max_rel, rel_err, small_cluster
+from tests.gpu_common import assert_close, small_cluster
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -67,10 +67,10 @@ def test_lowmodes_match_oracle(cluster):
     xh = g.grid["xhat"]
     w = g.grid["wnode"]
     ref = np.stack([coarse.restrict(f[g.sphere_nodes(k)], xh, w) for k in range(g.nb)])
-    assert max_rel(rho, ref) < 1e-12
+    assert_close(rho, ref, 1e-12)
     back = host(s.lowmodes_synth(dev(ref))).reshape(g.N, 3)
     refb = np.concatenate([coarse.prolong(ref[k], xh) for k in range(g.nb)])
-    assert max_rel(back, refb) < 1e-12
+    assert_close(back, refb, 1e-12)
 
 
 def _dataset(rng, B):
@@ -137,10 +137,10 @@ def test_precond_mlp_application_matches_oracle(cluster):
     rho = np.stack([coarse.restrict(r[g.sphere_nodes(k)], xh, wq) for k in range(g.nb)])
     zeta = coarse.coarse_apply(pairs, dirs, theta, rho)
     ref = m0_resistance(g, r) + np.concatenate([coarse.prolong(zeta[k], xh) for k in range(g.nb)])
-    assert rel_err(z, ref) < 1e-5, rel_err(z, ref)
+    assert_close(z, ref, 1e-5)
     # the M0 part alone is exact to rounding
     z0 = host(s.apply_precond(B.OP_DN_BIE, dev(r), precond=B.PC_M0)).reshape(g.N, 3)
-    assert rel_err(z0, m0_resistance(g, r)) < 1e-12
+    assert_close(z0, m0_resistance(g, r), 1e-12)
 
 
 def test_precond_mlp_mobility_application_matches_oracle(cluster):
@@ -162,7 +162,7 @@ def test_precond_mlp_mobility_application_matches_oracle(cluster):
     zeta = coarse.coarse_apply(pairs, dirs, theta, rho)
     corr = np.concatenate([coarse.prolong(zeta[k], xh) for k in range(g.nb)])
     d = (z1[:3 * g.N] - z0[:3 * g.N]).reshape(g.N, 3)
-    assert rel_err(d, corr) < 1e-5, rel_err(d, corr)
+    assert_close(d, corr, 1e-5)
     assert np.array_equal(z1[3 * g.N:], z0[3 * g.N:])
 
 
@@ -193,7 +193,8 @@ def test_trained_network_gain_over_m0():
         F2, T2, _, i2 = s.solve_resistance(wk["v"], wk["omega"], tol=1e-8, precision=B.MIXED, precond=B.PC_MLP)
         assert i0["converged"] and i1["converged"] and i2["converged"]
         assert i1["fallback_used"] == 0
-        assert rel_err(F1, F0) < 1e-6 and rel_err(F2, F0) < 1e-6
+        assert_close(F1, F0, 1e-6)
+        assert_close(F2, F0, 1e-6)
         m0.append(i0["iters"])
         ml.append(i1["iters"])
         mix.append(i2["iters"])
@@ -228,7 +229,8 @@ def test_trained_network_gain_over_m0_mobility():
         assert i0["converged"] and i1["converged"] and i2["converged"]
         assert i1["fallback_used"] == 0
         for v, o in ((v1, o1), (v2, o2)):
-            assert rel_err(v, v0) < 1e-6 and rel_err(o, o0) < 1e-6
+            assert_close(v, v0, 1e-6)
+            assert_close(o, o0, 1e-6)
         m0.append(i0["iters"])
         ml.append(i1["iters"])
         mix.append(i2["iters"])
@@ -253,5 +255,5 @@ def test_bad_network_falls_back_to_plain_gmres():
     F, T, _, info = s.solve_resistance(wk["v"], wk["omega"], tol=1e-8, precond=B.PC_MLP, max_iter=2000)
     F0, T0, _, i0 = s.solve_resistance(wk["v"], wk["omega"], tol=1e-8, precond=B.PC_NONE)
     assert info["converged"] and info["fallback_used"] == 1, info
-    assert rel_err(F, F0) < 1e-6
+    assert_close(F, F0, 1e-6)
     s.close()

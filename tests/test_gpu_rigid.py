@@ -11,7 +11,7 @@ import pytest
 from oracle import coarse, mlp, rigid
 from oracle.grid import Geometry
 from oracle.precond import m0_resistance
-from tests.gpu_common import rel_err, small_cluster
+from tests.gpu_common import assert_close, rel_err, small_cluster
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -42,7 +42,7 @@ def test_rigid_correction_matches_oracle(n, seed):
     z = host(s.apply_precond(B.OP_DN_BIE, dev(r), precond=B.PC_M0 | B.PC_RIGID)).reshape(g.N, 3)
     ref = rigid.correct(g, r, m0_resistance(g, r))
     # the coarse system is solved by conjugate gradients to relative residual 1e-7
-    assert rel_err(z, ref) < 1e-6, rel_err(z, ref)
+    assert_close(z, ref, 1e-6)
     # the correction is not small: it changes the rigid part of M0 r
     z0 = host(s.apply_precond(B.OP_DN_BIE, dev(r), precond=B.PC_M0)).reshape(g.N, 3)
     assert rel_err(z, z0) > 1e-3
@@ -66,7 +66,7 @@ def test_rigid_correction_on_the_learned_preconditioner():
     zeta = coarse.coarse_apply(pairs, dirs, theta, rho)
     # the rigid correction resets the rigid part of M0 r, the learned one is added after it
     ref = rigid.correct(g, r, m0_resistance(g, r)) + np.concatenate([coarse.prolong(zeta[k], xh) for k in range(g.nb)])
-    assert rel_err(z, ref) < 1e-5, rel_err(z, ref)
+    assert_close(z, ref, 1e-5)
     s.close()
 
 
@@ -76,7 +76,7 @@ def test_isolated_sphere_and_flag_rules():
     r = dev(np.random.default_rng(3).standard_normal(3 * s.N))
     z0 = host(s.apply_precond(B.OP_DN_BIE, r, precond=B.PC_M0))
     z1 = host(s.apply_precond(B.OP_DN_BIE, r, precond=B.PC_M0 | B.PC_RIGID))
-    assert rel_err(z1, z0) < 1e-12
+    assert_close(z1, z0, 1e-12)
     with pytest.raises(B.BieError):
         s.apply_precond(B.OP_DN_BIE, r, precond=B.PC_RIGID)
     s.close()
@@ -101,8 +101,8 @@ def test_rigid_solves_match_golden(precision):
     F, T, _, info = s.solve_resistance(w["v"], w["omega"], tol=1e-10, precision=precision,
                                        precond=B.PC_M0 | B.PC_RIGID)
     assert info["converged"] and info["rel_residual"] < 1e-10, info
-    assert rel_err(F, np.array(gold["resistance"]["F"])) < 1e-8
-    assert rel_err(T, np.array(gold["resistance"]["T"])) < 1e-8
+    assert_close(F, np.array(gold["resistance"]["F"]), 1e-8)
+    assert_close(T, np.array(gold["resistance"]["T"]), 1e-8)
     s.close()
 
 
@@ -120,7 +120,9 @@ def test_rigid_correction_gain_on_a_dilute_suspension():
     F2, T2, _, i2 = s.solve_resistance(v, om, tol=1e-8, precision=B.MIXED, precond=B.PC_M0 | B.PC_RIGID)
     assert i0["converged"] and i1["converged"] and i2["converged"]
     assert i1["fallback_used"] == 0 and i2["fallback_used"] == 0
-    assert rel_err(F1, F0) < 1e-6 and rel_err(T1, T0) < 1e-6 and rel_err(F2, F0) < 1e-6
+    assert_close(F1, F0, 1e-6)
+    assert_close(T1, T0, 1e-6)
+    assert_close(F2, F0, 1e-6)
     print(f"GMRES iterations: M0 {i0['iters']}, M0 + rigid {i1['iters']}, mixed M0 + rigid {i2['iters']}")
     assert i1["iters"] <= 0.7 * i0["iters"], (i0["iters"], i1["iters"])
     s.close()
@@ -142,7 +144,8 @@ def test_network_trained_on_the_rigid_base_gains_over_it():
         F0, T0, _, i0 = s.solve_resistance(wk["v"], wk["omega"], tol=1e-8, precond=B.PC_M0 | B.PC_RIGID)
         F1, T1, _, i1 = s.solve_resistance(wk["v"], wk["omega"], tol=1e-8, precond=B.PC_MLP | B.PC_RIGID)
         assert i0["converged"] and i1["converged"] and i1["fallback_used"] == 0
-        assert rel_err(F1, F0) < 1e-6 and rel_err(T1, T0) < 1e-6
+        assert_close(F1, F0, 1e-6)
+        assert_close(T1, T0, 1e-6)
         base.append(i0["iters"])
         learned.append(i1["iters"])
         s.close()

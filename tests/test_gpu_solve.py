@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from paper_1707_06551_amd.inputs import make_workload
-from tests.gpu_common import rel_err
+from tests.gpu_common import assert_close
 
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "spheres8_p8.json")
 
@@ -36,10 +36,10 @@ def test_solves_match_golden(precision, precond):
     s = bie.Spheres(w["centres"], 8, near_gap=1.0)
     F, T, _, info = s.solve_resistance(w["v"], w["omega"], tol=1e-10, precision=precision, precond=precond)
     assert info["converged"] and info["rel_residual"] < 1e-10, info
-    assert rel_err(F, np.array(g["resistance"]["F"])) < 1e-8
-    assert rel_err(T, np.array(g["resistance"]["T"])) < 1e-8
+    assert_close(F, np.array(g["resistance"]["F"]), 1e-8)
+    assert_close(T, np.array(g["resistance"]["T"]), 1e-8)
     v, om, _, info = s.solve_mobility(w["v"], w["omega"], tol=1e-10, precision=precision, precond=precond)
     assert info["converged"] and info["rel_residual"] < 1e-10, info
-    assert rel_err(v, np.array(g["mobility"]["v"])) < 1e-8
-    assert rel_err(om, np.array(g["mobility"]["omega"])) < 1e-8
+    assert_close(v, np.array(g["mobility"]["v"]), 1e-8)
+    assert_close(om, np.array(g["mobility"]["omega"]), 1e-8)
     s.close()
