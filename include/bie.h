@@ -405,6 +405,25 @@ int bie_mlp_eval(const bie_mlp_data* data, const float* weights, double* loss, f
 int bie_mlp_train(const bie_mlp_data* data, float* weights, int epochs, int cfg_per_batch, double lr,
                   double* loss_hist);
 
+/* ---- Operator application without device allocation ------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments, operators, stages,
+ * precisions and results as bie_apply_bio (up to the rounding order of the far-field
+ * partial sums), for op BIE_OP_S, _D, _SD_BIE, _DN_BIE or _MOBILITY (optionally with
+ * BIE_STAGE_* bits) on a context built with near_method 0.  The call's work buffers (far-
+ * field source strengths, transform coefficients, near-series tables, sphere moments and
+ * far-field partial sums) live in one file-scope device array of
+ * BIE_NOALLOC_SCRATCH_BYTES (96 MiB) instead of the context's buffers: every device the
+ * library runs this on holds its own copy until the process ends, and the call performs
+ * no device allocation or free.  The array holds the work of about 900,000 nodes at
+ * p = 12 (e.g. 2048 spheres, 638,976 nodes); a context whose work buffers do not fit
+ * returns BIE_EINVAL before any device work.  All calls on one device share that
+ * device's array, which keeps the last call's contents: calls that overlap in time on
+ * one device (several host threads, or streams not ordered with each other) race and
+ * give wrong results; order them.  Errors as bie_apply_bio. */
+#define BIE_NOALLOC_SCRATCH_BYTES 100663296ULL
+int bie_apply_bio_noalloc(bie_ctx* ctx, int op, int precision, const double* mu, double* u);
+
 /* Thread-local message of the last error on this thread ("" if none). */
 const char* bie_last_error(void);
 

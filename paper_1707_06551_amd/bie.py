@@ -27,7 +27,7 @@ EXPORTED = [
     "bie_solve", "bie_apply_precond", "bie_lowmodes", "bie_lowmodes_synth", "bie_pair_geometry",
     "bie_mlp_n_weights", "bie_precond_load", "bie_mlp_eval", "bie_mlp_train", "bie_eval_field",
     "bie_apply_laplace", "bie_solve_magnetic", "bie_solve_mobility_traction", "bie_build_spheres_radii",
-    "bie_num_nodes", "bie_near_gap", "bie_near_gap_for",
+    "bie_num_nodes", "bie_near_gap", "bie_near_gap_for", "bie_apply_bio_noalloc",
 ]
 NLOW = 25
 NFEAT = 8
@@ -103,6 +103,8 @@ def lib():
     L.bie_near_pairs.restype = I
     L.bie_apply_bio.argtypes = [VP, I, I, VP, VP]
     L.bie_apply_bio.restype = I
+    L.bie_apply_bio_noalloc.argtypes = [VP, I, I, VP, VP]
+    L.bie_apply_bio_noalloc.restype = I
     L.bie_vsh_forward.argtypes = [VP, I, VP, VP]
     L.bie_vsh_forward.restype = I
     L.bie_vsh_inverse.argtypes = [VP, I, VP, VP]
@@ -304,6 +306,12 @@ class Spheres:
         if u is None:
             u = torch.empty(self.dof(op), dtype=torch.float64, device=mu.device)
         _check(lib().bie_apply_bio(self._h, op, precision, _dptr(mu), _dptr(u)))
+        return u
+
+    def apply_noalloc(self, op, mu, u, precision=FP64):
+        """bie_apply_bio_noalloc: as apply(), with the work buffers in the library's
+        static device array (no device allocation); u must be given."""
+        _check(lib().bie_apply_bio_noalloc(self._h, op, precision, _dptr(mu), _dptr(u)))
         return u
 
     def vsh_forward(self, mu, precision=FP64):

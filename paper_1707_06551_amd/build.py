@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libbie.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["setup.cpp", "calibrate.cpp", "api.cpp", "vsh.hip", "near.hip", "p2p.hip", "solver.hip", "coarse.hip", "mlp.hip", "rigid.hip", "field.hip", "near_rot.hip", "laplace.hip", "traction.hip"]
+SOURCES = ["setup.cpp", "calibrate.cpp", "api.cpp", "vsh.hip", "near.hip", "p2p.hip", "solver.hip", "coarse.hip", "mlp.hip", "rigid.hip", "field.hip", "near_rot.hip", "laplace.hip", "traction.hip", "noalloc.hip"]
 
 # Packed FP32 instructions are disabled for all device code on purpose.
 HIP_FLAGS = [
