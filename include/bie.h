@@ -211,6 +211,16 @@ int bie_vsh_inverse(bie_ctx* ctx, int precision, const double* coef, double* u);
  * (BIE_EINVAL beyond).  Other forms ignore the flag (the mobility form carries its rigid motions as
  * unknowns with their own rows). */
 #define BIE_PC_RIGID 0x10
+/* Flag, OR-ed with BIE_PC_MLP (optionally with BIE_PC_RIGID): the learned correction
+ * acts on the residual that the base preconditioner leaves under the local part of the
+ * operator instead of on r itself:
+ *   z0 = B r,  z = z0 + P zeta(R (r - A_loc z0)),
+ * B = M0 (with the rigid-mode correction when BIE_PC_RIGID is set), A_loc the self term
+ * and the near-pair series of the operator (no far field), P, R, zeta as for
+ * BIE_PC_MLP.  Costs one transform and one near-series pass per application; needs
+ * weights trained for this composition (bie_precond_sample with the same flag).
+ * BIE_EINVAL without BIE_PC_MLP. */
+#define BIE_PC_LOCAL 0x20
 
 typedef struct {
   double tol;        /* stop when ||b - A x||_2 <= tol ||b||_2 (true residual)         */
@@ -367,6 +377,17 @@ int bie_lowmodes_synth(bie_ctx* ctx, const double* rho, double* f);
  * frames (count x 34: Q row-major then D2 row-major, D2_kl = tr(E_k Q E_l Q^T)). */
 int bie_pair_geometry(const bie_ctx* ctx, int64_t* count, int32_t* pair_i, int32_t* pair_j, float* feats,
                       double* frames);
+
+/* One training sample of the learned correction: for a right-hand side b and the
+ * solution x = A^-1 b of op (BIE_OP_DN_BIE or BIE_OP_MOBILITY; b, x device float64 of
+ * the solve's length), writes target = R x - R B b, the part of the low-mode response
+ * that the base preconditioner B misses, and the network's input xi = R b, or
+ * R (b - A_loc B b) when precond has BIE_PC_LOCAL (the composition the weights are
+ * trained for).  precond: BIE_PC_M0 (| BIE_PC_RIGID) (| BIE_PC_MLP, ignored)
+ * (| BIE_PC_LOCAL); xi, target: device float64, n_b x 25.  Unit spheres only.  Float64.
+ * Synchronises the stream. */
+int bie_precond_sample(bie_ctx* ctx, int op, int precond, const double* b, const double* x, double* xi,
+                       double* target);
 
 /* Number of MLP weights (flattened W1 8x64, b1, W2 64x64, b2, W3 64x278, b3). */
 int64_t bie_mlp_n_weights(void);

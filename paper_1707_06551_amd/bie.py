@@ -19,6 +19,7 @@ STAGE_SELF, STAGE_NEAR, STAGE_FAR = 0x100, 0x200, 0x400
 FP64, MIXED = 0, 1
 PC_NONE, PC_M0, PC_MLP = 0, 1, 2
 PC_RIGID = 0x10   # flag: global rigid-mode coarse correction (resistance form)
+PC_LOCAL = 0x20   # flag: learned correction on the base preconditioner's local residual
 OK, ENOCONV, EINVAL, EOVERLAP, EDEVICE, ENOMEM = 0, 1, -1, -2, -3, -4
 
 EXPORTED = [
@@ -27,7 +28,7 @@ EXPORTED = [
     "bie_solve", "bie_apply_precond", "bie_lowmodes", "bie_lowmodes_synth", "bie_pair_geometry",
     "bie_mlp_n_weights", "bie_precond_load", "bie_mlp_eval", "bie_mlp_train", "bie_eval_field",
     "bie_apply_laplace", "bie_solve_magnetic", "bie_solve_mobility_traction", "bie_build_spheres_radii",
-    "bie_num_nodes", "bie_near_gap", "bie_near_gap_for", "bie_apply_bio_noalloc",
+    "bie_num_nodes", "bie_near_gap", "bie_near_gap_for", "bie_apply_bio_noalloc", "bie_precond_sample",
 ]
 NLOW = 25
 NFEAT = 8
@@ -133,6 +134,8 @@ def lib():
     L.bie_lowmodes_synth.restype = I
     L.bie_pair_geometry.argtypes = [VP, P(I64), VP, VP, VP, VP]
     L.bie_pair_geometry.restype = I
+    L.bie_precond_sample.argtypes = [VP, I, I, VP, VP, VP, VP]
+    L.bie_precond_sample.restype = I
     L.bie_mlp_n_weights.argtypes = []
     L.bie_mlp_n_weights.restype = I64
     L.bie_precond_load.argtypes = [VP, VP, I64]
@@ -405,6 +408,14 @@ class Spheres:
         frames = np.empty((n, NFRAME), np.float64)
         _check(lib().bie_pair_geometry(self._h, ctypes.byref(cnt), _hptr(pi), _hptr(pj), _hptr(feats), _hptr(frames)))
         return pi, pj, feats, frames
+
+    def precond_sample(self, op, precond, b, x):
+        """bie_precond_sample: (xi, target), device tensors n_b x 25."""
+        import torch
+        xi = torch.empty(self.nb * NLOW, dtype=torch.float64, device=b.device)
+        t = torch.empty_like(xi)
+        _check(lib().bie_precond_sample(self._h, op, precond, _dptr(b), _dptr(x), _dptr(xi), _dptr(t)))
+        return xi, t
 
     def load_precond(self, weights):
         w = np.ascontiguousarray(weights, np.float32)

@@ -233,7 +233,9 @@ void apply_precond(bie_ctx* c, int op_base, int precision, int precond, const do
   if (precision != BIE_FP64 && precision != BIE_MIXED) throw Error{BIE_EINVAL, "bad precision"};
   const int64_t n = 3 * c->N + (op_base == BIE_OP_MOBILITY ? 6 * c->nb : 0);
   const bool rigid = (precond & BIE_PC_RIGID) != 0;
-  const int base = precond & ~BIE_PC_RIGID;
+  const bool local = (precond & BIE_PC_LOCAL) != 0;
+  const int base = precond & ~(BIE_PC_RIGID | BIE_PC_LOCAL);
+  if (local && base != BIE_PC_MLP) throw Error{BIE_EINVAL, "BIE_PC_LOCAL modifies BIE_PC_MLP only"};
   if (c->poly && base == BIE_PC_MLP)
     throw Error{BIE_EINVAL, "spheres of several radii: the learned correction is trained for unit spheres"};
   if (rigid && base == BIE_PC_NONE) throw Error{BIE_EINVAL, "BIE_PC_RIGID needs BIE_PC_M0 or BIE_PC_MLP"};
@@ -259,7 +261,49 @@ void apply_precond(bie_ctx* c, int op_base, int precision, int precond, const do
   // that a network trained on a base keeps its rigid-mode output.
   if (op_base == BIE_OP_SD_BIE || op_base == BIE_OP_KL_BIE) return;
   if (rigid && op_base == BIE_OP_DN_BIE) rigid_correct(c, r, z);
-  if (base == BIE_PC_MLP) coarse_correct(c, r, z);
+  if (base == BIE_PC_MLP) {
+    if (local) {
+      // the learned correction of the residual that z leaves under the self and
+      // near-series parts of the operator: w = r - A_loc z
+      if (c->pc_tmp.bytes < (size_t)n * sizeof(double)) c->pc_tmp.alloc((size_t)n * sizeof(double));
+      double* w = c->pc_tmp.as<double>();
+      apply(c, op_base | BIE_STAGE_SELF | BIE_STAGE_NEAR, precision, z, w);
+      dev_axpby(c, 1.0, r, -1.0, w, n);
+      coarse_correct(c, w, z);
+    } else {
+      coarse_correct(c, r, z);
+    }
+  }
+}
+
+// Training sample of the learned correction for one right-hand side b with solution
+// x = A^-1 b: target = R x - R z0, xi = R b, or R (b - A_loc z0) for BIE_PC_LOCAL, with
+// z0 = B b for the base preconditioner B (M0, optionally with the rigid correction).
+void precond_sample(bie_ctx* c, int op_base, int precond, const double* b, const double* x, double* xi,
+                    double* target) {
+  if (op_base != BIE_OP_DN_BIE && op_base != BIE_OP_MOBILITY)
+    throw Error{BIE_EINVAL, "training samples exist for BIE_OP_DN_BIE and BIE_OP_MOBILITY"};
+  if (c->poly) throw Error{BIE_EINVAL, "spheres of several radii: the learned correction is for unit spheres"};
+  const bool local = (precond & BIE_PC_LOCAL) != 0;
+  const int base = precond & ~(BIE_PC_LOCAL | BIE_PC_MLP);
+  if ((base & ~BIE_PC_RIGID) != BIE_PC_M0) throw Error{BIE_EINVAL, "the base of a training sample is BIE_PC_M0 (| BIE_PC_RIGID)"};
+  const int64_t n = 3 * c->N + (op_base == BIE_OP_MOBILITY ? 6 * c->nb : 0);
+  DevBuf z0, w;
+  z0.alloc((size_t)n * sizeof(double));
+  w.alloc((size_t)n * sizeof(double));
+  apply_precond(c, op_base, BIE_FP64, base, b, z0.as<double>());
+  // target = R (x - z0)
+  dev_copy(c, x, w.as<double>(), n);
+  dev_axpby(c, -1.0, z0.as<double>(), 1.0, w.as<double>(), n);
+  lowmode_restrict(c, w.as<double>(), target);
+  if (local) {
+    apply(c, op_base | BIE_STAGE_SELF | BIE_STAGE_NEAR, BIE_FP64, z0.as<double>(), w.as<double>());
+    dev_axpby(c, 1.0, b, -1.0, w.as<double>(), n);
+    lowmode_restrict(c, w.as<double>(), xi);
+  } else {
+    lowmode_restrict(c, b, xi);
+  }
+  BIE_HIP(hipStreamSynchronize(c->stream));
 }
 
 }  // namespace bie
@@ -665,6 +709,16 @@ int bie_pair_geometry(const bie_ctx* c, int64_t* count, int32_t* pair_i, int32_t
     }
   if (feats && np) std::memcpy(feats, c->pair_feat.data(), c->pair_feat.size() * sizeof(float));
   if (frames && np) std::memcpy(frames, c->pair_frame.data(), c->pair_frame.size() * sizeof(double));
+  return BIE_OK;
+}
+
+int bie_precond_sample(bie_ctx* c, int op, int precond, const double* b, const double* x, double* xi,
+                       double* target) {
+  if (!c || !b || !x || !xi || !target) {
+    bie::set_error("null argument");
+    return BIE_EINVAL;
+  }
+  BIE_TRY(bie::precond_sample(c, op, precond, b, x, xi, target));
   return BIE_OK;
 }
 

@@ -130,6 +130,7 @@ struct bie_ctx {
   bie::DevBuf dframe;               // device copy of pair_frame
   bie::DevBuf mlp_theta;            // near pairs x 278 float: MLP output
   bie::DevBuf rho, zeta;            // nb x 25 double
+  bie::DevBuf pc_tmp;               // solve-length work vector of BIE_PC_LOCAL (allocated on first use)
   bool theta_ready = false;
 
   // global rigid-mode coarse correction (rigid.hip), allocated on first use
@@ -230,6 +231,8 @@ double dev_norm(bie_ctx* c, const double* x, int64_t n);
 void dev_rigid_rhs(bie_ctx* c, const double* v_dev, const double* om_dev, double* b);
 void dev_precond_m0(bie_ctx* c, int op_base, int precision, const double* r, double* z);
 void apply_precond(bie_ctx* c, int op_base, int precision, int precond, const double* r, double* z);
+void precond_sample(bie_ctx* c, int op_base, int precond, const double* b, const double* x, double* xi,
+                    double* target);
 
 // learned coarse correction
 void build_coarse(bie_ctx* c);

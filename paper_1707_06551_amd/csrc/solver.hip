@@ -335,7 +335,8 @@ int solve(bie_ctx* c, int op, const double* b, double* x, int64_t n, const bie_s
   if (!(o.inner_tol > 0)) o.inner_tol = 1e-4;
   if (o.restart > 500) throw Error{BIE_EINVAL, "restart must be <= 500"};
   if (o.res_hist && o.res_hist_cap < 0) throw Error{BIE_EINVAL, "res_hist_cap must be >= 0"};
-  const int pc_base = o.precond & ~BIE_PC_RIGID;
+  const int pc_base = o.precond & ~(BIE_PC_RIGID | BIE_PC_LOCAL);
+  if ((o.precond & BIE_PC_LOCAL) && pc_base != BIE_PC_MLP) throw Error{BIE_EINVAL, "BIE_PC_LOCAL modifies BIE_PC_MLP only"};
   if (pc_base == BIE_PC_MLP && !c->theta_ready) throw Error{BIE_EINVAL, "BIE_PC_MLP needs bie_precond_load first"};
   if (pc_base < BIE_PC_NONE || pc_base > BIE_PC_MLP) throw Error{BIE_EINVAL, "unknown preconditioner"};
   if ((o.precond & BIE_PC_RIGID) && pc_base == BIE_PC_NONE)

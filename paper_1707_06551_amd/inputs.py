@@ -98,6 +98,20 @@ def place_spheres_radii(radii, box, min_gap, rng, max_tries=2_000_000):
     return out
 
 
+def window(centres, n, rng):
+    """n spheres cut out of a larger placement: the sphere nearest to a uniformly drawn
+    point of the middle half of the placement's bounding box, and its n - 1 nearest
+    neighbours (centre distance).  Gives small configurations with the neighbour
+    statistics of the bulk of a dense suspension, which random sequential addition of
+    n spheres in a small box cannot reach at the same volume fraction."""
+    c = np.asarray(centres, dtype=np.float64)
+    lo, hi = c.min(axis=0), c.max(axis=0)
+    x = lo + (hi - lo) * (0.25 + 0.5 * rng.random(3))
+    k0 = int(np.argmin(np.einsum("ij,ij->i", c - x, c - x)))
+    d = np.einsum("ij,ij->i", c - c[k0], c - c[k0])
+    return c[np.argsort(d, kind="stable")[:n]].copy()
+
+
 def make_workload(name, seed=0):
     """Centres and right-hand-side data of a named workload.
 

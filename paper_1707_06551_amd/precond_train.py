@@ -15,8 +15,16 @@ Applied at full strength the additive correction over-corrects, so a relaxation 
 (theta -> omega theta) is chosen on held-out configurations by GMRES iteration count
 and folded into the saved output layer.
 
+Composition (--composition): additive, z = B r + P zeta(R r) (BIE_PC_MLP), or local,
+z = z0 + P zeta(R (r - A_loc z0)) with z0 = B r and A_loc the self and near-series part
+of the operator (BIE_PC_MLP | BIE_PC_LOCAL).  The library forms each sample's input and
+target (bie_precond_sample).  --windows K trains on 64-sphere windows cut from
+1024-sphere placements at volume fraction 0.30 (K windows per placement), the bulk
+neighbour statistics of the dense 1024-sphere workload.
+
 Usage: python -m paper_1707_06551_amd.precond_train --configs 200 --rhs 4 --p 16 --epochs 400 [--base m0r]
        python -m paper_1707_06551_amd.precond_train --form mob --configs 200 --rhs 4 --p 12 --epochs 400
+       python -m paper_1707_06551_amd.precond_train --base m0r --composition local --windows 16 --configs 400
 """
 import argparse
 import json
@@ -56,15 +64,16 @@ DEFAULT_FILES = {"m0": DEFAULT_WEIGHTS, "m0r": os.path.join(HERE, "weights", "pr
 FORMS = {"dn": (bie.OP_DN_BIE, "spheres64_p16_train"), "mob": (bie.OP_MOBILITY, "spheres64_p12_slip_train")}
 
 
-def config_samples(sph, n_rhs, rng, tol=1e-8, base=bie.PC_M0, op=bie.OP_DN_BIE):
-    """(xi, target) of one configuration: (nb, n_rhs, 25) each, plus solve statistics."""
+def config_samples(sph, n_rhs, rng, tol=1e-8, base=bie.PC_M0, op=bie.OP_DN_BIE, local=False):
+    """(xi, target) of one configuration: (nb, n_rhs, 25) each, plus solve statistics.
+    The library forms both (bie_precond_sample): target = R x - R B b, xi = R b, or
+    R (b - A_loc B b) for the local-residual composition."""
     import torch
-    xi = rng.standard_normal((sph.nb, n_rhs, bie.NLOW))
+    xi = np.empty((sph.nb, n_rhs, bie.NLOW))
     target = np.empty_like(xi)
     iters = []
-    n3 = 3 * sph.N
     for r in range(n_rhs):
-        rho = torch.from_numpy(np.ascontiguousarray(xi[:, r, :]).reshape(-1)).cuda()
+        rho = torch.from_numpy(rng.standard_normal(sph.nb * bie.NLOW)).cuda()
         b = sph.lowmodes_synth(rho)
         if op == bie.OP_MOBILITY:
             b = torch.cat([b, torch.zeros(6 * sph.nb, dtype=b.dtype, device=b.device)])
@@ -72,22 +81,50 @@ def config_samples(sph, n_rhs, rng, tol=1e-8, base=bie.PC_M0, op=bie.OP_DN_BIE):
         if not info["converged"]:
             raise RuntimeError(f"training solve did not converge: {info}")
         iters.append(info["iters"])
-        z0 = sph.apply_precond(op, b, precond=base)
-        t = sph.lowmodes(x[:n3].contiguous()) - sph.lowmodes(z0[:n3].contiguous())
+        a, t = sph.precond_sample(op, base | (bie.PC_LOCAL if local else 0), b, x)
         torch.cuda.synchronize()
+        xi[:, r, :] = a.cpu().numpy().reshape(sph.nb, bie.NLOW)
         target[:, r, :] = t.cpu().numpy().reshape(sph.nb, bie.NLOW)
     return xi, target, iters
 
 
+def _placement(args):
+    """Centres of one large placement (random sequential addition), for windows."""
+    n, phi, gap, seed = args
+    from .inputs import box_side, place_spheres
+    return place_spheres(n, box_side(n, phi), gap, np.random.default_rng(seed))
+
+
+def window_configs(n_configs, per_placement, seed0, n=64, big=1024, phi=0.30, gap=0.02, procs=16):
+    """n-sphere windows of larger placements at volume fraction phi: ceil(n_configs /
+    per_placement) placements of `big` spheres (seeds seed0, seed0 + 1, ...; built in
+    parallel host processes before the GPU is used), per_placement windows each."""
+    import multiprocessing as mp
+    from .inputs import window
+    n_pl = (n_configs + per_placement - 1) // per_placement
+    with mp.get_context("fork").Pool(min(procs, n_pl)) as pool:
+        placements = pool.map(_placement, [(big, phi, gap, seed0 + k) for k in range(n_pl)])
+    out = []
+    for k, c in enumerate(placements):
+        rng = np.random.default_rng(seed0 + 7919 * (k + 1))
+        for _ in range(per_placement):
+            if len(out) < n_configs:
+                out.append(window(c, n, rng))
+    return out
+
+
 def build_set(n_configs, n_rhs, p, seed0=1000, workload="spheres64_p16_train", log=print, base=bie.PC_M0,
-              op=bie.OP_DN_BIE):
+              op=bie.OP_DN_BIE, local=False, windows=None):
+    """Training set of n_configs configurations: seeded placements of the training
+    workload, or the given list of window centres."""
     ts = bie.TrainingSet(n_rhs)
     t0 = time.time()
     for k in range(n_configs):
-        w = make_workload(workload, seed=seed0 + k)
-        sph = bie.Spheres(w["centres"], p, near_gap=1.0)
+        centres = windows[k] if windows is not None else make_workload(workload, seed=seed0 + k)["centres"]
+        sph = bie.Spheres(centres, p)
         pi, pj, feats, frames = sph.pair_geometry()
-        xi, target, iters = config_samples(sph, n_rhs, np.random.default_rng(seed0 + k + 7919), base=base, op=op)
+        xi, target, iters = config_samples(sph, n_rhs, np.random.default_rng(seed0 + k + 7919), base=base, op=op,
+                                           local=local)
         ts.add(pi, pj, feats, frames, xi, target)
         sph.close()
         if log and (k % 20 == 0 or k == n_configs - 1):
@@ -106,11 +143,12 @@ def scaled(w, omega):
 
 
 def select_relaxation(w, p, seeds, omegas=(0.1, 0.15, 0.2, 0.25, 0.3, 0.4, 0.6, 1.0), workload="spheres64_p16_train",
-                      log=print, base=bie.PC_M0):
-    """The additive correction over-corrects at full strength; choose the relaxation
-    omega (theta -> omega theta) that minimises the float64 GMRES iterations of the
-    workload's problem (resistance, or mobility with active slip) on held-out
-    configurations."""
+                      log=print, base=bie.PC_M0, local=False, windows=None):
+    """The correction can over-correct at full strength; choose the relaxation omega
+    (theta -> omega theta) that minimises the float64 GMRES iterations of the workload's
+    problem (resistance, or mobility with active slip) on held-out configurations: the
+    workload's placements for `seeds`, or the given window centres (resistance with the
+    rigid motions of the workload seeds)."""
     import torch
     table = {om: [] for om in omegas}
     base_its = []
@@ -120,9 +158,12 @@ def select_relaxation(w, p, seeds, omegas=(0.1, 0.15, 0.2, 0.25, 0.3, 0.4, 0.6, 
             return sph.solve_resistance(wk["v"], wk["omega"], tol=1e-8, precond=pc)[-1]["iters"]
         return sph.solve_mobility(wk["F"], wk["T"], slip=slip, tol=1e-8, precond=pc)[-1]["iters"]
 
-    for sd in seeds:
+    pc_mlp = bie.PC_MLP | (base & bie.PC_RIGID) | (bie.PC_LOCAL if local else 0)
+    for k, sd in enumerate(seeds):
         wk = make_workload(workload, seed=sd)
-        sph = bie.Spheres(wk["centres"], p, near_gap=1.0)
+        if windows is not None:
+            wk["centres"] = windows[k]
+        sph = bie.Spheres(wk["centres"], p)
         slip = None
         if wk["problem"] == "mobility_slip":
             xyz, _ = sph.nodes()
@@ -132,7 +173,7 @@ def select_relaxation(w, p, seeds, omegas=(0.1, 0.15, 0.2, 0.25, 0.3, 0.4, 0.6, 
         base_its.append(run(sph, wk, slip, base))
         for om in omegas:
             sph.load_precond(scaled(w, om))
-            table[om].append(run(sph, wk, slip, bie.PC_MLP | (base & bie.PC_RIGID)))
+            table[om].append(run(sph, wk, slip, pc_mlp))
         sph.close()
     best = min(omegas, key=lambda om: (sum(table[om]), om))
     if log:
@@ -165,15 +206,32 @@ def main():
                     help="preconditioner the correction is trained on top of (m0r: M0 + BIE_PC_RIGID, dn form only)")
     ap.add_argument("--form", choices=sorted(FORMS), default="dn",
                     help="dn: resistance (completed double-layer) form; mob: bordered mobility form with slip")
+    ap.add_argument("--composition", choices=["additive", "local"], default="additive",
+                    help="additive: z = B r + P zeta(R r); local: z = z0 + P zeta(R (r - A_loc z0)), z0 = B r "
+                         "(BIE_PC_LOCAL)")
+    ap.add_argument("--windows", type=int, default=0,
+                    help="> 0: train on 64-sphere windows of 1024-sphere placements at volume fraction 0.30 "
+                         "(this many windows per placement) instead of the workload's placements")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
     if args.form == "mob" and args.base != "m0":
         ap.error("the mobility form is trained on M0 only (BIE_PC_RIGID acts on the resistance form)")
+    if args.windows and args.form != "dn":
+        ap.error("windows are built for the resistance form")
     base = BASES[args.base]
+    local = args.composition == "local"
     op, workload = FORMS[args.form]
     out = args.out or DEFAULT_FILES["mob" if args.form == "mob" else args.base]
-    train = build_set(args.configs, args.rhs, args.p, seed0=1000, base=base, op=op, workload=workload)
-    hold = build_set(args.holdout, args.rhs, args.p, seed0=900000, base=base, op=op, workload=workload)
+    wtrain = whold = wsel = None
+    if args.windows:
+        # host work first (forked placement processes), then the GPU
+        wtrain = window_configs(args.configs, args.windows, seed0=1000)
+        whold = window_configs(args.holdout, args.windows, seed0=900000)
+        wsel = window_configs(args.select, args.windows, seed0=600000)
+    train = build_set(args.configs, args.rhs, args.p, seed0=1000, base=base, op=op, workload=workload, local=local,
+                      windows=wtrain)
+    hold = build_set(args.holdout, args.rhs, args.p, seed0=900000, base=base, op=op, workload=workload, local=local,
+                     windows=whold)
     w0 = init_weights(0)
     l0, _ = hold.eval(w0)
     t0 = time.time()
@@ -182,9 +240,12 @@ def main():
     l1, _ = hold.eval(w)
     ltr, _ = train.eval(w)
     omega, table, base_its = select_relaxation(w, args.p, seeds=[600000 + k for k in range(args.select)], base=base,
-                                               workload=workload)
-    meta = dict(version=1, formulation="MOBILITY" if args.form == "mob" else "DN_BIE", base=args.base,
-                workload=workload, p=args.p, hidden=HIDDEN, nfeat=bie.NFEAT, nout=278,
+                                               workload=workload, local=local, windows=wsel)
+    meta = dict(version=2, formulation="MOBILITY" if args.form == "mob" else "DN_BIE", base=args.base,
+                composition=args.composition, workload=workload,
+                windows=(f"64-sphere windows of 1024-sphere placements, phi 0.30, {args.windows} per placement"
+                         if args.windows else None),
+                p=args.p, hidden=HIDDEN, nfeat=bie.NFEAT, nout=278,
                 configs=args.configs, rhs=args.rhs, epochs=args.epochs, lr=args.lr, batch=args.batch,
                 train_loss=float(ltr), holdout_loss_init=float(l0), holdout_loss=float(l1),
                 train_seconds=t_train, relaxation=omega, relaxation_scan=table, base_iters=base_its,

@@ -22,14 +22,15 @@ from . import bie
 from .inputs import make_workload, slip_field
 
 PRECONDS = {"none": bie.PC_NONE, "m0": bie.PC_M0, "mlp": bie.PC_MLP, "m0r": bie.PC_M0 | bie.PC_RIGID,
-            "mlpr": bie.PC_MLP | bie.PC_RIGID}
+            "mlpr": bie.PC_MLP | bie.PC_RIGID, "mlpl": bie.PC_MLP | bie.PC_LOCAL,
+            "mlprl": bie.PC_MLP | bie.PC_RIGID | bie.PC_LOCAL}
 
 
-def solve_one(w, precision, precond, tol, weights=None, max_iter=3000, formulation="bordered"):
+def solve_one(w, precision, precond, tol, weights=None, max_iter=3000, formulation="bordered", near_gap=None):
     import torch
     t0 = time.perf_counter()
-    s = bie.Spheres(w["centres"], w["p"], near_gap=1.0)
-    if (precond & ~bie.PC_RIGID) == bie.PC_MLP:
+    s = bie.Spheres(w["centres"], w["p"], near_gap=near_gap)
+    if precond & bie.PC_MLP:
         s.load_precond(weights)
     slip = None
     if w["problem"] == "mobility_slip":
@@ -75,14 +76,18 @@ def main():
     ap.add_argument("--weights", default=None, help="MLP weights (.npz) for mlp / mlpr")
     ap.add_argument("--formulation", choices=["bordered", "traction"], default="bordered",
                     help="mobility workloads: bordered S + D form or the paper's K + L form (Eq. 5.8)")
+    ap.add_argument("--near-gap", type=float, default=0.0,
+                    help="d* of Eq. 4.5 (<= 0: measured for the default precision 1e-8)")
     args = ap.parse_args()
     precision = bie.MIXED if args.precision == "mixed" else bie.FP64
     precond = PRECONDS[args.precond]
     weights = None
-    if args.precond in ("mlp", "mlpr"):
+    if args.precond.startswith("mlp"):
         from .precond_train import DEFAULT_FILES, load_weights
         from .inputs import WORKLOADS
-        if args.precond == "mlpr":
+        if args.precond in ("mlpl", "mlprl") and not args.weights:
+            ap.error("the local-residual composition needs --weights trained for it")
+        if args.precond.startswith("mlpr"):
             key = "m0r"
         else:
             key = "m0" if WORKLOADS[args.workload]["problem"] == "resistance" else "mob"
@@ -90,7 +95,8 @@ def main():
     rows = []
     for k in range(args.seeds):
         w = make_workload(args.workload, seed=args.seed0 + k)
-        r = solve_one(w, precision, precond, args.tol, weights, formulation=args.formulation)
+        r = solve_one(w, precision, precond, args.tol, weights, formulation=args.formulation,
+                      near_gap=args.near_gap if args.near_gap > 0 else None)
         rows.append(r)
         print(json.dumps(dict(workload=args.workload, precision=args.precision, precond=args.precond,
                               formulation=args.formulation, **r)), flush=True)

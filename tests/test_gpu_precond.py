@@ -9,6 +9,7 @@ import pytest
 
 from oracle import coarse, mlp
 from oracle.grid import Geometry
+from oracle.operators import Operators
 from oracle.precond import m0_resistance
 from tests.gpu_common import assert_close, small_cluster
 
@@ -164,6 +165,51 @@ def test_precond_mlp_mobility_application_matches_oracle(cluster):
     d = (z1[:3 * g.N] - z0[:3 * g.N]).reshape(g.N, 3)
     assert_close(d, corr, 1e-5)
     assert np.array_equal(z1[3 * g.N:], z0[3 * g.N:])
+
+
+def _local_dn(g, z):
+    """The self term (1/2 I + D_pv) and the near series of the double layer at z."""
+    ops = Operators(g)
+    return ops.self_part(z, 0.0, 1.0) + 0.5 * z + ops.near_part(z, 0.0, 1.0)
+
+
+def test_precond_local_application_matches_oracle(cluster):
+    # BIE_PC_LOCAL: z = z0 + P zeta(R (r - A_loc z0)), z0 = M0 r, A_loc = self + near
+    c, p, s, g = cluster
+    B = _bie()
+    w = mlp.init_weights(23, out_scale=0.2)
+    s.load_precond(w.astype(np.float32))
+    rng = np.random.default_rng(10)
+    r = rng.standard_normal((g.N, 3))
+    z = host(s.apply_precond(B.OP_DN_BIE, dev(r), precond=B.PC_MLP | B.PC_LOCAL)).reshape(g.N, 3)
+    z0 = m0_resistance(g, r)
+    wres = r - _local_dn(g, z0)
+    pairs, feats, dirs = coarse.pair_features(c, g.near, 1.0)
+    theta, _ = mlp.forward(w.astype(np.float32).astype(np.float64), feats.astype(np.float32).astype(np.float64))
+    xh, wq = g.grid["xhat"], g.grid["wnode"]
+    rho = np.stack([coarse.restrict(wres[g.sphere_nodes(k)], xh, wq) for k in range(g.nb)])
+    zeta = coarse.coarse_apply(pairs, dirs, theta, rho)
+    ref = z0 + np.concatenate([coarse.prolong(zeta[k], xh) for k in range(g.nb)])
+    assert_close(z, ref, 1e-5)
+    with pytest.raises(B.BieError):
+        s.apply_precond(B.OP_DN_BIE, dev(r), precond=B.PC_M0 | B.PC_LOCAL)
+
+
+@pytest.mark.parametrize("local", [False, True])
+def test_training_sample_matches_oracle(cluster, local):
+    # bie_precond_sample: target = R x - R M0 b, xi = R b or R (b - A_loc M0 b)
+    c, p, s, g = cluster
+    B = _bie()
+    rng = np.random.default_rng(11)
+    b = rng.standard_normal((g.N, 3))
+    x = rng.standard_normal((g.N, 3))
+    xi, t = s.precond_sample(B.OP_DN_BIE, B.PC_M0 | (B.PC_LOCAL if local else 0), dev(b), dev(x))
+    xh, wq = g.grid["xhat"], g.grid["wnode"]
+    z0 = m0_resistance(g, b)
+    R = lambda f: np.stack([coarse.restrict(f[g.sphere_nodes(k)], xh, wq) for k in range(g.nb)])
+    assert_close(host(t).reshape(g.nb, 25), R(x) - R(z0), 1e-11)
+    ref_xi = R(b - _local_dn(g, z0)) if local else R(b)
+    assert_close(host(xi).reshape(g.nb, 25), ref_xi, 1e-11)
 
 
 def test_nonfinite_weights_are_rejected(cluster):
