@@ -186,7 +186,8 @@ def main():
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="spheres2048_p12_slip")
-    ap.add_argument("--precond", choices=["m0", "mlp"], default="m0")
+    ap.add_argument("--precond", choices=["m0", "mlp", "m0r", "mlpr"], default="m0",
+                    help="m0r / mlpr: with the rigid-mode coarse correction (resistance workloads)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 reference solves")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -227,10 +228,14 @@ def main():
     w0 = ws[0]
     p = w0["p"]
     mobility = w0["problem"].startswith("mobility")
-    pc = bie.PC_M0 if args.precond == "m0" else bie.PC_MLP
+    pc = {"m0": bie.PC_M0, "mlp": bie.PC_MLP, "m0r": bie.PC_M0 | bie.PC_RIGID,
+          "mlpr": bie.PC_MLP | bie.PC_RIGID}[args.precond]
+    if (pc & bie.PC_RIGID) and mobility:
+        ap.error("the rigid-mode correction acts on the resistance form")
     weights = None
-    if pc == bie.PC_MLP:
+    if pc & bie.PC_MLP:
         weights, _meta = load_weights(os.path.join(ROOT, "paper_1707_06551_amd", "weights",
+                                                   "precond_dn_rigid.npz" if pc & bie.PC_RIGID else
                                                    MLP_WEIGHTS["mobility" if mobility else "resistance"]))
     ctx, slips, t_setup = [], [], []
     for w in ws:
@@ -333,8 +338,9 @@ def main():
         "config": {"workload": w0["name"], "n_spheres": w0["n"], "p": p, "nodes": s0.N, "seeds": n_seeds,
                    "problem": w0["problem"], "tol": w0["tol"],
                    "precision": "mixed (f32 P2P/SHT, f64 near+GMRES)",
-                   "precond": "M0 (isolated-sphere inverse)" if pc == bie.PC_M0 else
-                              "M0 + learned close-pair correction",
+                   "precond": {"m0": "M0 (isolated-sphere inverse)", "mlp": "M0 + learned close-pair correction",
+                               "m0r": "M0 + rigid-mode coarse correction",
+                               "mlpr": "M0 + rigid-mode + learned corrections"}[args.precond],
                    "volume_fraction": w0.get("phi"), "min_gap": w0["min_gap"],
                    "near_gap": s0.near_gap, "near_tol": s0.near_tol, "near_pairs_seed0": n_near},
         "time_to_solution_s": tts,
