@@ -72,7 +72,8 @@ struct R4 {
 // KIND: 1 = Stokeslet, 2 = double layer, 3 = Stokeslet + double layer, 4 = single-layer
 // traction K (Eq. 2.22, normal of the TARGET node).  Constants:
 //   S:   (1/8pi) [q/r + r (r.q)/r^3]            -> c = (r.q) / r^3
-//   D:   (3/4pi) r (r.q)(r.n)/r^5               -> c = (r.q)(r.n) / r^5, r.n = -(p.o~)/2 - 1
+//   D:   (3/4pi) r (r.q)(r.n)/r^5               -> c = (r.q)(2 + p.o~) / r^5 = -2 (r.q)(r.n) / r^5,
+//        the factor -1/2 applied once to the sum (an exact power-of-two scaling)
 //   S+D: (1/8pi) [q/r + r (r.q)/r^3 (1 + 6 (r.n)/r^2)]  -> c = (r.q)/r^3 (3 (|p|^2 - 1)/r^2 - 2)
 //   K:   -(3/4pi) r (r.q)(r.n_x)/r^5            -> c = (r.q)(r.n_x) / r^5, with
 //        r.n_x = p.n_x - o.n_x = K3 + o~.(n_x / 2), K3 = p.n_x formed once per (target,
@@ -85,8 +86,8 @@ __device__ __forceinline__ void pair(R px, R py, R pz, R K, R K3, R tnx, R tny, 
                                      const R4<R>& q, R& C, R& Cx, R& Cy, R& Cz, R& Qx, R& Qy, R& Qz) {
   R r2, d2 = 0;
   if (KIND == 2) {
-    d2 = fma(pz, o.z, fma(py, o.y, px * o.x));   // -2 p.o
-    r2 = K + d2;
+    d2 = fma(pz, o.z, fma(py, o.y, fma(px, o.x, (R)2)));   // 2 - 2 p.o = -2 r.n
+    r2 = K + d2;                                           // K = |p|^2 - 1
   } else {
     r2 = fma(pz, o.z, fma(py, o.y, fma(px, o.x, K)));
   }
@@ -97,8 +98,7 @@ __device__ __forceinline__ void pair(R px, R py, R pz, R K, R K3, R tnx, R tny, 
   if (KIND == 1) {
     c = rq * ir * ir2;
   } else if (KIND == 2) {
-    const R rn = fma((R)-0.5, d2, (R)-1);
-    c = (rq * rn) * (ir2 * ir2 * ir);
+    c = (rq * d2) * (ir2 * ir2 * ir);
   } else if (KIND == 4) {
     const R rn = fma(o.z, tnz, fma(o.y, tny, fma(o.x, tnx, K3)));
     c = (rq * rn) * (ir2 * ir2 * ir);
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(256) void far_kernel(FarParams a) {
         pz[k] = (R)dz + oxt[k][2];
         tcv[k] = (R)-2;
       }
-      K[k] = fma(px[k], px[k], fma(py[k], py[k], fma(pz[k], pz[k], (R)1)));
+      K[k] = fma(px[k], px[k], fma(py[k], py[k], fma(pz[k], pz[k], (R)(KIND == 2 ? -1 : 1))));
       if (KIND == 4)
         K3[k] = fma(px[k], oxt[k][0], fma(py[k], oxt[k][1], pz[k] * oxt[k][2]));
       else
@@ -273,12 +273,13 @@ __global__ __launch_bounds__(256) void far_kernel(FarParams a) {
       }
     }
   }
+  const double cs = KIND == 2 ? -0.5 * a.cscale : a.cscale;
 #pragma unroll
   for (int k = 0; k < TPL; ++k) {
     if (!valid[k]) continue;
     double* out = a.partial + ((int64_t)blockIdx.y * a.N + g[k]) * 3;
     for (int d = 0; d < 3; ++d)
-      out[d] = a.cscale * ((double)tot[k][d] - (double)comp[k][d]) + (1.0 / (8.0 * M_PI)) * cpl[k][d];
+      out[d] = cs * ((double)tot[k][d] - (double)comp[k][d]) + (1.0 / (8.0 * M_PI)) * cpl[k][d];
   }
 }
 
