@@ -234,9 +234,11 @@ def main():
         ap.error("the rigid-mode correction acts on the resistance form")
     weights = None
     if pc & bie.PC_MLP:
-        weights, _meta = load_weights(os.path.join(ROOT, "paper_1707_06551_amd", "weights",
-                                                   "precond_dn_rigid.npz" if pc & bie.PC_RIGID else
-                                                   MLP_WEIGHTS["mobility" if mobility else "resistance"]))
+        weights, meta = load_weights(os.path.join(ROOT, "paper_1707_06551_amd", "weights",
+                                                  "precond_dn_rigid.npz" if pc & bie.PC_RIGID else
+                                                  MLP_WEIGHTS["mobility" if mobility else "resistance"]))
+        if meta.get("composition") == "local":
+            pc |= bie.PC_LOCAL
     ctx, slips, t_setup = [], [], []
     for w in ws:
         t0 = time.perf_counter()

@@ -194,8 +194,9 @@ int bie_vsh_inverse(bie_ctx* ctx, int precision, const double* coef, double* u);
 #define BIE_PC_MLP 2  /* M0 plus the learned close-pair coarse correction              */
 /* Flag, OR-ed with BIE_PC_M0 or BIE_PC_MLP: global rigid-mode coarse correction of the
  * resistance form (no counterpart in the paper).  With z0 = M0 r, z = z0 + P (y - R z0)
- * with M_RPY S y = R r (with BIE_PC_MLP the learned correction is then added to z, so
- * weights for this combination are trained on that base): R projects each sphere's field onto
+ * with M_RPY S y = R r (with BIE_PC_MLP the learned correction is then added to z, acting
+ * on the 19 non-rigid low modes only - the rigid ones are this correction's - so weights
+ * for this combination are trained on that base): R projects each sphere's field onto
  * its six rigid modes (W_1, X_1 of Definition 2.2; a = int f / 4 pi, b = 3 int x x f /
  * 8 pi), P (a, b) = a + b x x, S = diag(4 pi, 8 pi / 3) turns them into the force and
  * torque the completion flow of Eqs. 5.18-5.19 carries, and M_RPY is the Rotne-Prager-
@@ -218,8 +219,9 @@ int bie_vsh_inverse(bie_ctx* ctx, int precision, const double* coef, double* u);
  * B = M0 (with the rigid-mode correction when BIE_PC_RIGID is set), A_loc the self term
  * and the near-pair series of the operator (no far field), P, R, zeta as for
  * BIE_PC_MLP.  Costs one transform and one near-series pass per application; needs
- * weights trained for this composition (bie_precond_sample with the same flag).
- * BIE_EINVAL without BIE_PC_MLP. */
+ * weights trained for this composition (bie_precond_sample with the same flag).  With
+ * BIE_PC_RIGID the learned part acts on the non-rigid low modes, as with the additive
+ * composition.  BIE_EINVAL without BIE_PC_MLP. */
 #define BIE_PC_LOCAL 0x20
 
 typedef struct {
@@ -384,7 +386,8 @@ int bie_pair_geometry(const bie_ctx* ctx, int64_t* count, int32_t* pair_i, int32
  * that the base preconditioner B misses, and the network's input xi = R b, or
  * R (b - A_loc B b) when precond has BIE_PC_LOCAL (the composition the weights are
  * trained for).  precond: BIE_PC_M0 (| BIE_PC_RIGID) (| BIE_PC_MLP, ignored)
- * (| BIE_PC_LOCAL); xi, target: device float64, n_b x 25.  Unit spheres only.  Float64.
+ * (| BIE_PC_LOCAL); with BIE_PC_RIGID (resistance form) the rigid components (b, c) of
+ * xi and target are zero.  xi, target: device float64, n_b x 25.  Unit spheres only.  Float64.
  * Synchronises the stream. */
 int bie_precond_sample(bie_ctx* ctx, int op, int precond, const double* b, const double* x, double* xi,
                        double* target);

@@ -82,6 +82,11 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing; build it with `python -m paper_1707_06551_amd.build`")
+    # torch ships its own HIP runtime under the same soname as the system one that the
+    # library links: importing torch first makes the library bind to torch's copy, so the
+    # process holds one runtime (device pointers and streams cross between the two).
+    # Loaded the other way round the process would hold two, and torch's finds no device.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     P, I, I64, D, VP = ctypes.POINTER, ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
     L.bie_build_spheres.argtypes = [VP, I64, P(Opts), P(VP)]

@@ -260,7 +260,8 @@ void apply_precond(bie_ctx* c, int op_base, int precision, int precond, const do
   // resistance and mobility forms (weights are trained per form) and is added last, so
   // that a network trained on a base keeps its rigid-mode output.
   if (op_base == BIE_OP_SD_BIE || op_base == BIE_OP_KL_BIE) return;
-  if (rigid && op_base == BIE_OP_DN_BIE) rigid_correct(c, r, z);
+  const bool rigid_on = rigid && op_base == BIE_OP_DN_BIE;
+  if (rigid_on) rigid_correct(c, r, z);
   if (base == BIE_PC_MLP) {
     if (local) {
       // the learned correction of the residual that z leaves under the self and
@@ -269,9 +270,9 @@ void apply_precond(bie_ctx* c, int op_base, int precision, int precond, const do
       double* w = c->pc_tmp.as<double>();
       apply(c, op_base | BIE_STAGE_SELF | BIE_STAGE_NEAR, precision, z, w);
       dev_axpby(c, 1.0, r, -1.0, w, n);
-      coarse_correct(c, w, z);
+      coarse_correct(c, w, z, rigid_on);
     } else {
-      coarse_correct(c, r, z);
+      coarse_correct(c, r, z, rigid_on);
     }
   }
 }
@@ -302,6 +303,11 @@ void precond_sample(bie_ctx* c, int op_base, int precond, const double* b, const
     lowmode_restrict(c, w.as<double>(), xi);
   } else {
     lowmode_restrict(c, b, xi);
+  }
+  if ((base & BIE_PC_RIGID) && op_base == BIE_OP_DN_BIE) {
+    // with the rigid-mode correction the learned part acts on the non-rigid modes
+    zero_rigid_modes(c, xi);
+    zero_rigid_modes(c, target);
   }
   BIE_HIP(hipStreamSynchronize(c->stream));
 }

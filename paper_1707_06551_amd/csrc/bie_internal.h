@@ -238,7 +238,10 @@ void precond_sample(bie_ctx* c, int op_base, int precond, const double* b, const
 void build_coarse(bie_ctx* c);
 void lowmode_restrict(bie_ctx* c, const double* f, double* rho);
 void lowmode_prolong(bie_ctx* c, const double* rho, double* f, bool accumulate);
-void coarse_correct(bie_ctx* c, const double* r, double* z);
+// skip_rigid: the learned part acts on the non-rigid low modes only (the rigid ones are
+// the global rigid-mode correction's)
+void coarse_correct(bie_ctx* c, const double* r, double* z, bool skip_rigid);
+void zero_rigid_modes(bie_ctx* c, double* rho);
 
 // global rigid-mode coarse correction: z <- z + P (A_c^-1 R r - R z)
 constexpr int64_t RIGID_MAX_SPHERES = 65536;

@@ -211,18 +211,25 @@ __global__ void k_prolong(const double* rho, const double* F, int P, int64_t N, 
 }
 
 // zeta_i = sum_{e in close(i)} rot_e^T [K_off(theta_e) rot_e rho_j + K_self(theta_e) rot_e rho_i]
+// skip_rigid: the rigid modes (b, c: translations and rotations) are left to the global
+// rigid-mode correction: they are dropped from rho and from zeta (the rotation into the
+// pair frame maps each of the two vector blocks onto itself, so dropping them in the
+// global frame is dropping them in every pair frame).
 __global__ void k_coarse_apply(const double* rho, const int* close_ptr, const int* close_idx, const double* frames,
-                               const float* theta, int64_t nb, double* zeta) {
+                               const float* theta, int64_t nb, int skip_rigid, double* zeta) {
   const int64_t sph = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (sph >= nb) return;
-  double z[25];
-  for (int m = 0; m < 25; ++m) z[m] = 0.0;
-  const double* ri = rho + (int64_t)sph * 25;
+  double z[25], ri[25];
+  for (int m = 0; m < 25; ++m) {
+    z[m] = 0.0;
+    ri[m] = (skip_rigid && m >= kIB && m < kITV) ? 0.0 : rho[(int64_t)sph * 25 + m];
+  }
   for (int e = close_ptr[sph]; e < close_ptr[sph + 1]; ++e) {
     const int j = close_idx[e];
     const double* fr = frames + (size_t)e * kFrame;
-    double y[25], x[25], c[25], back[25];
-    rot25_apply<double>(fr, rho + (int64_t)j * 25, y, false);
+    double rj[25], y[25], x[25], c[25], back[25];
+    for (int m = 0; m < 25; ++m) rj[m] = (skip_rigid && m >= kIB && m < kITV) ? 0.0 : rho[(int64_t)j * 25 + m];
+    rot25_apply<double>(fr, rj, y, false);
     rot25_apply<double>(fr, ri, x, false);
     for (int m = 0; m < 25; ++m) c[m] = 0.0;
     apply_K<double, float>(theta + (size_t)e * kNTheta2, y, c);
@@ -230,7 +237,17 @@ __global__ void k_coarse_apply(const double* rho, const int* close_ptr, const in
     rot25_apply<double>(fr, c, back, true);
     for (int m = 0; m < 25; ++m) z[m] += back[m];
   }
-  for (int m = 0; m < 25; ++m) zeta[(int64_t)sph * 25 + m] = z[m];
+  for (int m = 0; m < 25; ++m) zeta[(int64_t)sph * 25 + m] = (skip_rigid && m >= kIB && m < kITV) ? 0.0 : z[m];
+}
+
+__global__ void k_zero_rigid(double* rho, int64_t nb) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nb * 6) rho[(i / 6) * 25 + kIB + i % 6] = 0.0;
+}
+
+void zero_rigid_modes(bie_ctx* c, double* rho) {
+  k_zero_rigid<<<dim3((unsigned)((c->nb * 6 + 255) / 256)), dim3(256), 0, c->stream>>>(rho, c->nb);
+  BIE_HIP(hipGetLastError());
 }
 
 void lowmode_restrict(bie_ctx* c, const double* f, double* rho) {
@@ -246,12 +263,12 @@ void lowmode_prolong(bie_ctx* c, const double* rho, double* f, bool accumulate) 
 }
 
 // z += P zeta(R r): the learned part of the MLP preconditioner (z already holds M0 r)
-void coarse_correct(bie_ctx* c, const double* r, double* z) {
+void coarse_correct(bie_ctx* c, const double* r, double* z, bool skip_rigid) {
   if (!c->theta_ready || c->close_idx.empty()) return;
   lowmode_restrict(c, r, c->rho.as<double>());
   k_coarse_apply<<<dim3((unsigned)((c->nb + 63) / 64)), dim3(64), 0, c->stream>>>(
       c->rho.as<double>(), c->dclose_ptr.as<int>(), c->dclose_idx.as<int>(), c->dframe.as<double>(),
-      c->mlp_theta.as<float>(), c->nb, c->zeta.as<double>());
+      c->mlp_theta.as<float>(), c->nb, skip_rigid ? 1 : 0, c->zeta.as<double>());
   BIE_HIP(hipGetLastError());
   lowmode_prolong(c, c->zeta.as<double>(), z, true);
 }

@@ -24,7 +24,8 @@ neighbour statistics of the dense 1024-sphere workload.
 
 Usage: python -m paper_1707_06551_amd.precond_train --configs 200 --rhs 4 --p 16 --epochs 400 [--base m0r]
        python -m paper_1707_06551_amd.precond_train --form mob --configs 200 --rhs 4 --p 12 --epochs 400
-       python -m paper_1707_06551_amd.precond_train --base m0r --composition local --windows 16 --configs 400
+       python -m paper_1707_06551_amd.precond_train --base m0r --composition local --windows 16 --configs 500 \
+           --select 1 --select-workload spheres1024_p16 --omegas 0.075,0.1,0.125,0.15 --procs 6
 """
 import argparse
 import json
@@ -102,8 +103,12 @@ def window_configs(n_configs, per_placement, seed0, n=64, big=1024, phi=0.30, ga
     import multiprocessing as mp
     from .inputs import window
     n_pl = (n_configs + per_placement - 1) // per_placement
-    with mp.get_context("fork").Pool(min(procs, n_pl)) as pool:
-        placements = pool.map(_placement, [(big, phi, gap, seed0 + k) for k in range(n_pl)])
+    jobs = [(big, phi, gap, seed0 + k) for k in range(n_pl)]
+    if procs <= 1 or n_pl == 1:
+        placements = [_placement(j) for j in jobs]
+    else:
+        with mp.get_context("fork").Pool(min(procs, n_pl)) as pool:
+            placements = pool.map(_placement, jobs)
     out = []
     for k, c in enumerate(placements):
         rng = np.random.default_rng(seed0 + 7919 * (k + 1))
@@ -113,22 +118,50 @@ def window_configs(n_configs, per_placement, seed0, n=64, big=1024, phi=0.30, ga
     return out
 
 
-def build_set(n_configs, n_rhs, p, seed0=1000, workload="spheres64_p16_train", log=print, base=bie.PC_M0,
-              op=bie.OP_DN_BIE, local=False, windows=None):
-    """Training set of n_configs configurations: seeded placements of the training
-    workload, or the given list of window centres."""
-    ts = bie.TrainingSet(n_rhs)
-    t0 = time.time()
-    for k in range(n_configs):
-        centres = windows[k] if windows is not None else make_workload(workload, seed=seed0 + k)["centres"]
+def _samples_of(job):
+    """Samples of configurations ks (one GPU process): [(pi, pj, feats, frames, xi, target, iters)]."""
+    ks, centres_list, n_rhs, p, seed0, base, op, local = job
+    out = []
+    for k, centres in zip(ks, centres_list):
         sph = bie.Spheres(centres, p)
         pi, pj, feats, frames = sph.pair_geometry()
         xi, target, iters = config_samples(sph, n_rhs, np.random.default_rng(seed0 + k + 7919), base=base, op=op,
                                            local=local)
-        ts.add(pi, pj, feats, frames, xi, target)
         sph.close()
-        if log and (k % 20 == 0 or k == n_configs - 1):
-            log(f"config {k + 1}/{n_configs}: {len(pi)} pairs, solve iters {iters}, {time.time() - t0:.1f} s")
+        out.append((pi, pj, feats, frames, xi, target, iters))
+    return out
+
+
+def build_set(n_configs, n_rhs, p, seed0=1000, workload="spheres64_p16_train", log=print, base=bie.PC_M0,
+              op=bie.OP_DN_BIE, local=False, windows=None, procs=1, chunk=8):
+    """Training set of n_configs configurations: seeded placements of the training
+    workload, or the given list of window centres.  procs > 1 solves chunks of
+    configurations in that many GPU processes at once (small systems leave the GPU mostly
+    idle between launches); the set is the same for any procs."""
+    ts = bie.TrainingSet(n_rhs)
+    t0 = time.time()
+    centres = [windows[k] if windows is not None else make_workload(workload, seed=seed0 + k)["centres"]
+               for k in range(n_configs)]
+    jobs = [(list(range(a, min(a + chunk, n_configs))), centres[a:a + chunk], n_rhs, p, seed0, base, op, local)
+            for a in range(0, n_configs, chunk)]
+    if procs > 1:
+        import multiprocessing as mp
+        pool = mp.get_context("spawn").Pool(procs)
+        results = pool.imap(_samples_of, jobs)
+    else:
+        pool, results = None, map(_samples_of, jobs)
+    done = 0
+    try:
+        for res in results:
+            for (pi, pj, feats, frames, xi, target, iters) in res:
+                ts.add(pi, pj, feats, frames, xi, target)
+                done += 1
+            if log:
+                log(f"configs {done}/{n_configs}: {len(pi)} pairs, solve iters {iters}, {time.time() - t0:.1f} s")
+    finally:
+        if pool is not None:
+            pool.close()
+            pool.join()
     return ts
 
 
@@ -143,7 +176,7 @@ def scaled(w, omega):
 
 
 def select_relaxation(w, p, seeds, omegas=(0.1, 0.15, 0.2, 0.25, 0.3, 0.4, 0.6, 1.0), workload="spheres64_p16_train",
-                      log=print, base=bie.PC_M0, local=False, windows=None):
+                      log=print, base=bie.PC_M0, local=False, windows=None, precision=bie.FP64):
     """The correction can over-correct at full strength; choose the relaxation omega
     (theta -> omega theta) that minimises the float64 GMRES iterations of the workload's
     problem (resistance, or mobility with active slip) on held-out configurations: the
@@ -155,8 +188,12 @@ def select_relaxation(w, p, seeds, omegas=(0.1, 0.15, 0.2, 0.25, 0.3, 0.4, 0.6, 
 
     def run(sph, wk, slip, pc):
         if wk["problem"] == "resistance":
-            return sph.solve_resistance(wk["v"], wk["omega"], tol=1e-8, precond=pc)[-1]["iters"]
-        return sph.solve_mobility(wk["F"], wk["T"], slip=slip, tol=1e-8, precond=pc)[-1]["iters"]
+            info = sph.solve_resistance(wk["v"], wk["omega"], tol=1e-8, precond=pc, precision=precision)[-1]
+        else:
+            info = sph.solve_mobility(wk["F"], wk["T"], slip=slip, tol=1e-8, precond=pc, precision=precision)[-1]
+        if log:
+            log(f"  selection: seed {wk['seed']}, precond {pc:#x}: {info['iters']} iterations")
+        return info["iters"]
 
     pc_mlp = bie.PC_MLP | (base & bie.PC_RIGID) | (bie.PC_LOCAL if local else 0)
     for k, sd in enumerate(seeds):
@@ -212,6 +249,11 @@ def main():
     ap.add_argument("--windows", type=int, default=0,
                     help="> 0: train on 64-sphere windows of 1024-sphere placements at volume fraction 0.30 "
                          "(this many windows per placement) instead of the workload's placements")
+    ap.add_argument("--select-workload", default=None,
+                    help="choose the relaxation on this workload's placements (seeds 1..select, mixed precision) "
+                         "instead of held-out training configurations")
+    ap.add_argument("--omegas", default="0.1,0.15,0.2,0.25,0.3,0.4,0.6,1.0", help="relaxations scanned")
+    ap.add_argument("--procs", type=int, default=1, help="GPU processes forming the training samples")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
     if args.form == "mob" and args.base != "m0":
@@ -227,11 +269,19 @@ def main():
         # host work first (forked placement processes), then the GPU
         wtrain = window_configs(args.configs, args.windows, seed0=1000)
         whold = window_configs(args.holdout, args.windows, seed0=900000)
-        wsel = window_configs(args.select, args.windows, seed0=600000)
+        if not args.select_workload:
+            wsel = window_configs(args.select, args.windows, seed0=600000)
+    omegas = tuple(float(x) for x in args.omegas.split(","))
+    if args.select_workload:
+        sel = dict(seeds=list(range(1, 1 + args.select)), workload=args.select_workload, windows=None,
+                   precision=bie.MIXED)
+    else:
+        sel = dict(seeds=[600000 + k for k in range(args.select)], workload=workload, windows=wsel,
+                   precision=bie.FP64)
     train = build_set(args.configs, args.rhs, args.p, seed0=1000, base=base, op=op, workload=workload, local=local,
-                      windows=wtrain)
+                      windows=wtrain, procs=args.procs)
     hold = build_set(args.holdout, args.rhs, args.p, seed0=900000, base=base, op=op, workload=workload, local=local,
-                     windows=whold)
+                     windows=whold, procs=args.procs)
     w0 = init_weights(0)
     l0, _ = hold.eval(w0)
     t0 = time.time()
@@ -239,12 +289,14 @@ def main():
     t_train = time.time() - t0
     l1, _ = hold.eval(w)
     ltr, _ = train.eval(w)
-    omega, table, base_its = select_relaxation(w, args.p, seeds=[600000 + k for k in range(args.select)], base=base,
-                                               workload=workload, local=local, windows=wsel)
+    omega, table, base_its = select_relaxation(w, args.p, omegas=omegas, base=base, local=local, **sel)
     meta = dict(version=2, formulation="MOBILITY" if args.form == "mob" else "DN_BIE", base=args.base,
                 composition=args.composition, workload=workload,
                 windows=(f"64-sphere windows of 1024-sphere placements, phi 0.30, {args.windows} per placement"
                          if args.windows else None),
+                selection=(f"{args.select_workload} seeds 1-{args.select}, mixed precision" if args.select_workload
+                           else f"{args.select} held-out training configurations, float64"),
+                rigid_modes=("left to the rigid-mode correction" if base & bie.PC_RIGID else "included"),
                 p=args.p, hidden=HIDDEN, nfeat=bie.NFEAT, nout=278,
                 configs=args.configs, rhs=args.rhs, epochs=args.epochs, lr=args.lr, batch=args.batch,
                 train_loss=float(ltr), holdout_loss_init=float(l0), holdout_loss=float(l1),

@@ -85,13 +85,13 @@ def main():
     if args.precond.startswith("mlp"):
         from .precond_train import DEFAULT_FILES, load_weights
         from .inputs import WORKLOADS
-        if args.precond in ("mlpl", "mlprl") and not args.weights:
-            ap.error("the local-residual composition needs --weights trained for it")
         if args.precond.startswith("mlpr"):
             key = "m0r"
         else:
             key = "m0" if WORKLOADS[args.workload]["problem"] == "resistance" else "mob"
-        weights = load_weights(args.weights or DEFAULT_FILES[key])[0]
+        weights, meta = load_weights(args.weights or DEFAULT_FILES[key])
+        if meta.get("composition") == "local":
+            precond |= bie.PC_LOCAL
     rows = []
     for k in range(args.seeds):
         w = make_workload(args.workload, seed=args.seed0 + k)
