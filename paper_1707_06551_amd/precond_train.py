@@ -19,8 +19,9 @@ Composition (--composition): additive, z = B r + P zeta(R r) (BIE_PC_MLP), or lo
 z = z0 + P zeta(R (r - A_loc z0)) with z0 = B r and A_loc the self and near-series part
 of the operator (BIE_PC_MLP | BIE_PC_LOCAL).  The library forms each sample's input and
 target (bie_precond_sample).  --windows K trains on 64-sphere windows cut from
-1024-sphere placements at volume fraction 0.30 (K windows per placement), the bulk
-neighbour statistics of the dense 1024-sphere workload.
+1024-sphere placements (K windows per placement) at the volume fraction of the form's
+large workload (0.30 for the resistance form, 0.25 for the mobility form with slip): the
+bulk neighbour statistics of the dense suspension.
 
 Usage: python -m paper_1707_06551_amd.precond_train --configs 200 --rhs 4 --p 16 --epochs 400 [--base m0r]
        python -m paper_1707_06551_amd.precond_train --form mob --configs 200 --rhs 4 --p 12 --epochs 400
@@ -258,19 +259,20 @@ def main():
     args = ap.parse_args()
     if args.form == "mob" and args.base != "m0":
         ap.error("the mobility form is trained on M0 only (BIE_PC_RIGID acts on the resistance form)")
-    if args.windows and args.form != "dn":
-        ap.error("windows are built for the resistance form")
     base = BASES[args.base]
     local = args.composition == "local"
     op, workload = FORMS[args.form]
     out = args.out or DEFAULT_FILES["mob" if args.form == "mob" else args.base]
     wtrain = whold = wsel = None
+    # windows: 64-sphere windows of 1024-sphere placements at the volume fraction of the
+    # form's large workload (resistance 0.30, mobility with slip 0.25)
+    wphi = 0.30 if args.form == "dn" else 0.25
     if args.windows:
         # host work first (forked placement processes), then the GPU
-        wtrain = window_configs(args.configs, args.windows, seed0=1000)
-        whold = window_configs(args.holdout, args.windows, seed0=900000)
+        wtrain = window_configs(args.configs, args.windows, seed0=1000, phi=wphi)
+        whold = window_configs(args.holdout, args.windows, seed0=900000, phi=wphi)
         if not args.select_workload:
-            wsel = window_configs(args.select, args.windows, seed0=600000)
+            wsel = window_configs(args.select, args.windows, seed0=600000, phi=wphi)
     omegas = tuple(float(x) for x in args.omegas.split(","))
     if args.select_workload:
         sel = dict(seeds=list(range(1, 1 + args.select)), workload=args.select_workload, windows=None,
@@ -292,7 +294,7 @@ def main():
     omega, table, base_its = select_relaxation(w, args.p, omegas=omegas, base=base, local=local, **sel)
     meta = dict(version=2, formulation="MOBILITY" if args.form == "mob" else "DN_BIE", base=args.base,
                 composition=args.composition, workload=workload,
-                windows=(f"64-sphere windows of 1024-sphere placements, phi 0.30, {args.windows} per placement"
+                windows=(f"64-sphere windows of 1024-sphere placements, phi {wphi:.2f}, {args.windows} per placement"
                          if args.windows else None),
                 selection=(f"{args.select_workload} seeds 1-{args.select}, mixed precision" if args.select_workload
                            else f"{args.select} held-out training configurations, float64"),
