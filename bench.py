@@ -6,7 +6,7 @@ mobility problem of Section 5, Problem 4, Eqs. 5.14-5.17, in the bordered second
 form); 16 seeded configurations.  One step = one solve of one configuration (step i
 solves seed i mod 16) to relative residual 1e-8 with float32 transforms and far-field
 sums inside float64 GMRES with iterative refinement, and the isolated-sphere block
-preconditioner (optionally with the learned close-pair correction).  Near pairs use the
+preconditioner with the learned close-pair correction (--precond m0: without it).  Near pairs use the
 separation threshold of Eq. 4.5 measured for the requested precision 1e-8.  Every
 context is built and every input is resident on the device before the timed region
 (set-up time reported apart).  value = far-field pair interactions evaluated by the
@@ -20,7 +20,7 @@ device time of each step of the hot path, and the CPU oracle: its far-field dire
 on a bounded sample of target nodes across the host's cores, and its full solve of the
 8-sphere workload beside the library's.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--precond m0|mlp]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--precond m0|mlp|m0r|mlpr]
 """
 import argparse
 import json
@@ -186,13 +186,16 @@ def main():
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="spheres2048_p12_slip")
-    ap.add_argument("--precond", choices=["m0", "mlp", "m0r", "mlpr"], default="m0",
-                    help="m0r / mlpr: with the rigid-mode coarse correction (resistance workloads)")
+    ap.add_argument("--precond", choices=["m0", "mlp", "m0r", "mlpr"], default=None,
+                    help="default: mlp (M0 + the learned correction) on the 2048-sphere slip workload, m0 elsewhere; "
+                         "m0r / mlpr: with the rigid-mode coarse correction (resistance workloads)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 reference solves")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (HBM byte-counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()
+    if args.precond is None:
+        args.precond = "mlp" if args.workload == "spheres2048_p12_slip" else "m0"
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (the far field would shard "
               "by target spheres with one all-gather of the source strengths per matvec)",
