@@ -43,6 +43,14 @@ __device__ inline double wsum(double v) {
   return v;
 }
 
+// 1/sqrt(x): the hardware estimate (5e-8 relative) and one Newton step, y (3 - x y^2) / 2
+// (4e-15); a fraction of the instructions of a float64 division and square root.
+__device__ inline double rsqrt_f64(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double h = x * y;
+  return fma(0.5 * y, fma(-h, y, 1.0), y);
+}
+
 // Block-wide sum of v (256 threads); every thread gets the result.
 __device__ inline double block_sum256(double v, double* lds) {
   v = wsum(v);
@@ -134,14 +142,14 @@ __global__ __launch_bounds__(256) void k_rpy_matvec(const double* centres4, cons
     }
     const double rx = cx - sc[e][0], ry = cy - sc[e][1], rz = cz - sc[e][2];
     const double d2 = rx * rx + ry * ry + rz * rz;
-    const double id = 1.0 / sqrt(d2);
+    const double id = rsqrt_f64(d2);
     const double id2 = id * id, id3 = id2 * id;
     const double rF = rx * Fx + ry * Fy + rz * Fz;
     const double rT = rx * Tx + ry * Ty + rz * Tz;
     // translation: (1/8pi)[(1/d + s/(3d^3)) F + (1/d - s/d^3)(e.F) e - (r x T)/d^3],
     // s = a_i^2 + a_k^2 (2 for unit spheres)
     const double s2 = ai * ai + sc[e][3];
-    const double c1 = id + (s2 / 3.0) * id3;
+    const double c1 = id + (s2 * (1.0 / 3.0)) * id3;
     const double c2 = (id - s2 * id3) * id2 * rF;
     a[0] += k8 * (c1 * Fx + c2 * rx - id3 * (ry * Tz - rz * Ty));
     a[1] += k8 * (c1 * Fy + c2 * ry - id3 * (rz * Tx - rx * Tz));
