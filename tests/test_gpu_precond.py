@@ -195,6 +195,54 @@ def test_precond_local_application_matches_oracle(cluster):
         s.apply_precond(B.OP_DN_BIE, dev(r), precond=B.PC_M0 | B.PC_LOCAL)
 
 
+def _local_mobility(g, xvec):
+    """The bordered mobility operator without its far field: self term, identity, near
+    series and the rigid-motion rows (density rows), plus the moment rows."""
+    ops = Operators(g)
+    mu = xvec[:3 * g.N].reshape(g.N, 3)
+    far = ops.far_part(mu, 1.0, 1.0).reshape(-1)
+    return ops.apply_mobility(xvec) - np.concatenate([far, np.zeros(6 * g.nb)])
+
+
+def test_precond_local_mobility_application_matches_oracle(cluster):
+    # BIE_PC_LOCAL on the bordered mobility form: z = z0 + [P zeta(R (r - A_loc z0)); 0]
+    # with z0 = M0 r and A_loc the self term, the near series and the bordered rows
+    c, p, s, g = cluster
+    B = _bie()
+    w = mlp.init_weights(29, out_scale=0.2)
+    s.load_precond(w.astype(np.float32))
+    rng = np.random.default_rng(12)
+    r = rng.standard_normal(3 * g.N + 6 * g.nb)
+    z = host(s.apply_precond(B.OP_MOBILITY, dev(r), precond=B.PC_MLP | B.PC_LOCAL))
+    z0 = host(s.apply_precond(B.OP_MOBILITY, dev(r), precond=B.PC_M0))
+    wres = (r - _local_mobility(g, z0))[:3 * g.N].reshape(g.N, 3)
+    pairs, feats, dirs = coarse.pair_features(c, g.near, 1.0)
+    theta, _ = mlp.forward(w.astype(np.float32).astype(np.float64), feats.astype(np.float32).astype(np.float64))
+    xh, wq = g.grid["xhat"], g.grid["wnode"]
+    rho = np.stack([coarse.restrict(wres[g.sphere_nodes(k)], xh, wq) for k in range(g.nb)])
+    zeta = coarse.coarse_apply(pairs, dirs, theta, rho)
+    corr = np.concatenate([coarse.prolong(zeta[k], xh) for k in range(g.nb)])
+    assert_close((z[:3 * g.N] - z0[:3 * g.N]).reshape(g.N, 3), corr, 1e-5)
+    assert np.array_equal(z[3 * g.N:], z0[3 * g.N:])
+
+
+def test_training_sample_mobility_local_matches_oracle(cluster):
+    # bie_precond_sample on the bordered form: target = R (x - M0 b), xi = R (b - A_loc M0 b),
+    # both on the density part
+    c, p, s, g = cluster
+    B = _bie()
+    rng = np.random.default_rng(13)
+    b = rng.standard_normal(3 * g.N + 6 * g.nb)
+    x = rng.standard_normal(3 * g.N + 6 * g.nb)
+    xi, t = s.precond_sample(B.OP_MOBILITY, B.PC_M0 | B.PC_LOCAL, dev(b), dev(x))
+    z0 = host(s.apply_precond(B.OP_MOBILITY, dev(b), precond=B.PC_M0))
+    xh, wq = g.grid["xhat"], g.grid["wnode"]
+    dens = lambda v: v[:3 * g.N].reshape(g.N, 3)
+    R = lambda f: np.stack([coarse.restrict(f[g.sphere_nodes(k)], xh, wq) for k in range(g.nb)])
+    assert_close(host(t).reshape(g.nb, 25), R(dens(x - z0)), 1e-11)
+    assert_close(host(xi).reshape(g.nb, 25), R(dens(b - _local_mobility(g, z0))), 1e-11)
+
+
 @pytest.mark.parametrize("local", [False, True])
 def test_training_sample_matches_oracle(cluster, local):
     # bie_precond_sample: target = R x - R M0 b, xi = R b or R (b - A_loc M0 b)
