@@ -229,7 +229,8 @@ typedef struct {
   int restart;       /* Krylov dimension per cycle (<= 0 selects 100, > 500 BIE_EINVAL) */
   int max_iter;      /* total inner iterations (<= 0 selects 1000)                      */
   int precision;     /* BIE_FP64 or BIE_MIXED                                           */
-  int precond;       /* BIE_PC_NONE, _M0 or _MLP, optionally | BIE_PC_RIGID             */
+  int precond;       /* BIE_PC_NONE, _M0 or _MLP, optionally | BIE_PC_RIGID (resistance
+                        form), BIE_PC_MLP optionally | BIE_PC_LOCAL                      */
   double inner_tol;  /* BIE_MIXED inner tolerance (<= 0 selects 1e-4)                   */
   const double* x0;  /* initial guess (device float64, the solve's own unknown vector:
                         psi (3N) for resistance, [mu; v; omega] (3N + 6 n_b) for the
