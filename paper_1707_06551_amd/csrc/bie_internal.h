@@ -115,7 +115,8 @@ struct bie_ctx {
   bie::DevBuf partial;         // nsplit x N x 3 double: far-field partial sums
   bie::DevBuf moments;         // nb x 6 double: int mu, int (y - c) x mu
   bie::DevBuf scal;            // small scratch for reductions
-  int nsplit = 1;
+  int nsplit = 1;              // source splits the partial-sum buffer holds (upper bound per launch)
+  int num_cus = 256;           // compute units of the device
 
   // solver work space (allocated on first solve)
   bie::DevBuf krylov, zbasis, vec[6];

@@ -295,20 +295,49 @@ __global__ void reduce_partials(const double* partial, int nsplit, int64_t n3, d
 // vs scalar 13.8 ms; float64 LDS 22.4 ms vs scalar 21.0 ms.  float32 stages sources in
 // LDS, float64 reads them through the scalar cache (float64 VALU issues at one rate
 // with or without SGPR operands).
-template <typename R, int KIND>
-static void far_launch(bie_ctx* c, const FarParams& a, dim3 grid) {
+// Source splits of one launch.  The work-groups (grid.x target blocks x splits, all of
+// about equal work) run in rounds of `slots` resident ones; the count whose rounds are
+// fullest is taken, the fewest splits among equals, between the count that gives ~6144
+// work-groups and the capacity of the partial-sum buffer.
+static int far_splits(int64_t nb, int64_t tblocks, int cap, int64_t slots) {
+  const int lo = (int)std::max<int64_t>(1, std::min<int64_t>({(6144 + tblocks - 1) / tblocks, nb / 2, (int64_t)cap}));
+  int best = lo;
+  double best_eff = -1.0;
+  for (int ns = lo; ns <= cap; ++ns) {
+    const int64_t per = (nb + ns - 1) / ns;
+    const int64_t used = (nb + per - 1) / per;
+    const int64_t w = tblocks * used;
+    const double eff = (double)w / (double)(((w + slots - 1) / slots) * slots);
+    if (eff > best_eff + 1e-9) {
+      best_eff = eff;
+      best = ns;
+    }
+  }
+  return best;
+}
+
+template <typename R, int KIND, int SRC, bool RADII>
+static int far_launch_one(bie_ctx* c, FarParams& a, int64_t tblocks, size_t sm) {
   constexpr int TPL = 2;
+  int per_cu = 0;
+  BIE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, far_kernel<R, KIND, TPL, SRC, RADII>, 256, sm));
+  const int64_t slots = (int64_t)std::max(1, per_cu) * c->num_cus;
+  const int ns = far_splits(c->nb, tblocks, c->nsplit, slots);
+  a.sph_per_split = (int)((c->nb + ns - 1) / ns);
+  const int used = (int)((c->nb + a.sph_per_split - 1) / a.sph_per_split);
+  far_kernel<R, KIND, TPL, SRC, RADII><<<dim3((unsigned)tblocks, (unsigned)used), dim3(256), sm, c->stream>>>(a);
+  return used;
+}
+
+template <typename R, int KIND>
+static int far_launch(bie_ctx* c, FarParams& a, int64_t tblocks) {
   if constexpr (sizeof(R) == 8) {
-    if (c->poly)
-      far_kernel<R, KIND, TPL, 1, true><<<grid, dim3(256), 0, c->stream>>>(a);
-    else
-      far_kernel<R, KIND, TPL, 1, false><<<grid, dim3(256), 0, c->stream>>>(a);
+    return c->poly ? far_launch_one<R, KIND, 1, true>(c, a, tblocks, 0)
+                   : far_launch_one<R, KIND, 1, false>(c, a, tblocks, 0);
   } else {
     const size_t sm = 2 * (size_t)c->P * sizeof(R4<R>);
-    if (c->poly)
-      far_kernel<R, KIND, TPL, 0, true><<<grid, dim3(256), sm, c->stream>>>(a);
-    else
-      far_kernel<R, KIND, TPL, 0, false><<<grid, dim3(256), sm, c->stream>>>(a);
+    return c->poly ? far_launch_one<R, KIND, 0, true>(c, a, tblocks, sm)
+                   : far_launch_one<R, KIND, 0, false>(c, a, tblocks, sm);
   }
 }
 
@@ -328,23 +357,22 @@ void launch_far(bie_ctx* c, int precision, const OpSpec& spec, double* u) {
   a.nb = c->nb;
   a.P = c->P;
   a.nwords = c->nwords;
-  a.sph_per_split = (int)((c->nb + c->nsplit - 1) / c->nsplit);
   a.completion = spec.completion ? 1 : 0;
-  const int nsplit = (int)((c->nb + a.sph_per_split - 1) / a.sph_per_split);
   const int kind = spec.traction ? 4 : (spec.a_s != 0.0 ? 1 : 0) + (spec.a_d != 0.0 ? 2 : 0);
   a.cscale = (kind == 2) ? 3.0 / (4.0 * M_PI) : (kind == 4) ? -3.0 / (4.0 * M_PI) : 1.0 / (8.0 * M_PI);
-  dim3 grid((unsigned)((c->N + 256 * TPL - 1) / (256 * TPL)), (unsigned)nsplit);
+  const int64_t tblocks = (c->N + 256 * TPL - 1) / (256 * TPL);
   if (kind == 0) throw Error{BIE_EINVAL, "empty far-field kernel"};
+  int nsplit = 1;
   if (f32) {
-    if (kind == 1) far_launch<float, 1>(c, a, grid);
-    if (kind == 2) far_launch<float, 2>(c, a, grid);
-    if (kind == 3) far_launch<float, 3>(c, a, grid);
-    if (kind == 4) far_launch<float, 4>(c, a, grid);
+    if (kind == 1) nsplit = far_launch<float, 1>(c, a, tblocks);
+    if (kind == 2) nsplit = far_launch<float, 2>(c, a, tblocks);
+    if (kind == 3) nsplit = far_launch<float, 3>(c, a, tblocks);
+    if (kind == 4) nsplit = far_launch<float, 4>(c, a, tblocks);
   } else {
-    if (kind == 1) far_launch<double, 1>(c, a, grid);
-    if (kind == 2) far_launch<double, 2>(c, a, grid);
-    if (kind == 3) far_launch<double, 3>(c, a, grid);
-    if (kind == 4) far_launch<double, 4>(c, a, grid);
+    if (kind == 1) nsplit = far_launch<double, 1>(c, a, tblocks);
+    if (kind == 2) nsplit = far_launch<double, 2>(c, a, tblocks);
+    if (kind == 3) nsplit = far_launch<double, 3>(c, a, tblocks);
+    if (kind == 4) nsplit = far_launch<double, 4>(c, a, tblocks);
   }
   BIE_HIP(hipGetLastError());
   const int64_t n3 = 3 * c->N;
