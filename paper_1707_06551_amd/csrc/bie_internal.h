@@ -189,6 +189,8 @@ void launch_near_rot(bie_ctx* c, const OpSpec& spec, double* u);
 void series_radial(double a_s, double a_d, int p, double* kvv, double* kww, double* kwv, double* kxx);
 int near_table_slots(int p, int mmax);
 std::vector<int> near_launch_order(const std::vector<int>& near_ptr, int64_t nb);
+// Source splits the far-field partial-sum buffer is sized for (N nodes, nb spheres).
+int far_split_capacity(int64_t N, int64_t nb);
 void launch_far(bie_ctx* c, int precision, const OpSpec& spec, double* u);
 void apply(bie_ctx* c, int op, int precision, const double* mu, double* u);
 

@@ -295,6 +295,14 @@ __global__ void reduce_partials(const double* partial, int nsplit, int64_t n3, d
 // vs scalar 13.8 ms; float64 LDS 22.4 ms vs scalar 21.0 ms.  float32 stages sources in
 // LDS, float64 reads them through the scalar cache (float64 VALU issues at one rate
 // with or without SGPR operands).
+// Capacity of the partial-sum buffer in source splits: up to 64 (at most one split per
+// two spheres), so that the split count of a launch can make its last round of resident
+// work-groups full (64 x N x 24 B: ~1 GB at 640,000 nodes).
+int far_split_capacity(int64_t N, int64_t nb) {
+  (void)N;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(64, nb / 2));
+}
+
 // Source splits of one launch.  The work-groups (grid.x target blocks x splits, all of
 // about equal work) run in rounds of `slots` resident ones; the count whose rounds are
 // fullest is taken, the fewest splits among equals, between the count that gives ~6144

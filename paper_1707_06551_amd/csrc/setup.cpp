@@ -464,14 +464,10 @@ void build(bie_ctx* c, const double* centres, const double* radii, int64_t nb, c
   c->q.alloc((size_t)c->N * 4 * sizeof(double));
   c->moments.alloc((size_t)nb * 6 * sizeof(double));
   c->scal.alloc(262144 * sizeof(double));  // [0,1024) scalars, [1024,...) dot partials, [200000,...) Krylov host-exchange
-  // far-field source splits: room for up to twice the ~6144 work-groups that fill the
-  // device several times over; each launch picks the count whose last round of
-  // resident work-groups is fullest (launch_far)
+  // far-field source splits: each launch picks its count (launch_far), up to this capacity
   BIE_HIP(hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, c->device));
   c->num_cus = std::max(1, c->num_cus);
-  const int64_t tblocks = (c->N + 511) / 512;
-  int ns = (int)std::max<int64_t>(1, std::min<int64_t>(2 * ((6144 + tblocks - 1) / tblocks), nb / 2));
-  c->nsplit = std::max(1, std::min(ns, 64));
+  c->nsplit = far_split_capacity(c->N, nb);
   c->partial.alloc((size_t)c->nsplit * c->N * 3 * sizeof(double));
   upload_vec(c->tlat_d, tt);
   if (!c->near_idx.empty()) {
