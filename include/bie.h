@@ -121,7 +121,12 @@ int bie_near_gap_for(int p, int n_phi, double tol, double* d_star);
  * uploads it to the device.  centres: host, n_spheres x 3 row-major.  Fails with
  * BIE_EOVERLAP when two centres are closer than 2 (overlapping spheres), BIE_EINVAL
  * on bad options, BIE_ENOMEM / BIE_EDEVICE on allocation or device errors.  Blocks
- * until the upload completes.  *out is owned by the caller and released by bie_free. */
+ * until the upload completes.  *out is owned by the caller and released by bie_free.
+ * Device memory held: besides the tables and per-node fields, the far field's
+ * partial-sum buffer of min(64, n_spheres / 2) source splits x 3N doubles (about
+ * 1 GB at 640,000 nodes), from which each far-field launch uses the split count that
+ * fills the device's last round of work-groups; the solver's Krylov basis is
+ * allocated on the first solve. */
 int bie_build_spheres(const double* centres, int64_t n_spheres, const bie_opts* opts, bie_ctx** out);
 
 /* As bie_build_spheres for spheres of radii a_k (host, n_spheres, each in [1/16, 16];
